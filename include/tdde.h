@@ -1,0 +1,186 @@
+/*
+ * tdde.h -- C ABI of the MI355X (gfx950) Crank-Nicolson / BiCGSTAB time step for the
+ * time-dependent Dirac equation in a spherical-spinor x B-spline basis.
+ *
+ * Method (arXiv 2512.21697, "GaDE"):
+ *   - Hamiltonian, eq. fullH:  H(t) = H0 + sum_m coef_m f_m(t) (K^a A_m K^b) (x) R_m
+ *     H0 (and the overlap S) are block diagonal over angular channels j and are polynomials
+ *     in the channel's kappa; A_m are sparse angular couplings, R_m banded radial matrices
+ *     (2x2 grid of bands over the large/small spinor components, Sec. 2.2).
+ *   - time step, eq. solPsi with the midpoint rule of Sec. 2.4:
+ *       (S + i dt/2 H(t_n + dt/2)) psi_{n+1} = (S - i dt/2 H(t_n + dt/2)) psi_n
+ *   - linear solve by BiCGSTAB (Sec. 2.4, Sec. 3.3), optionally right-preconditioned with
+ *     the LU factors of the block-diagonal M = S + i dt/2 H0 (eq. matrixM).
+ *   - time functions f_m(t): sin^2-envelope pulses (eq. ndpPot, dipole limit) and their
+ *     trigonometric factorisation (eq. bdpA).
+ *
+ * Conventions
+ *   - Complex numbers are interleaved (re, im) pairs: tdde_c128 / float pairs for c64.
+ *   - State vectors are device arrays laid out [batch][nang][2][nr] (instance, channel,
+ *     component s = 0 large / 1 small, radial index), contiguous, complex128 unless a
+ *     function says complex64. The caller owns them; the library never frees them and
+ *     never keeps a pointer past the call.
+ *   - Band arrays are host arrays [..][2][2][2*half_band+1][nr]: band[s][s'][d+hb][i]
+ *     multiplies x[s'][i+d] into y[s][i]; entries whose column falls outside [0, nr) must be 0.
+ *   - All work is enqueued on the stream given to tdde_create (a hipStream_t passed as void*,
+ *     NULL = default stream). Functions that return host statistics synchronise that stream.
+ *   - Every function returns a tdde_status; nothing throws across the ABI. On error the
+ *     context stays usable and tdde_last_error() describes the failure.
+ *   - Memory: tdde_assemble allocates every device buffer the context needs (operator copy,
+ *     Krylov workspace, preconditioner factors, reduction scratch). tdde_set_dt,
+ *     tdde_set_pulses, tdde_set_field, tdde_apply, tdde_solve, tdde_step, tdde_run_batched
+ *     allocate nothing.
+ */
+#ifndef TDDE_H
+#define TDDE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TDDE_OK = 0,
+  TDDE_NOT_CONVERGED = 1, /* max_iter reached; x holds the last iterate, stats are filled      */
+  TDDE_BREAKDOWN = 2,     /* repeated BiCGSTAB breakdown (rho or omega vanished after restart)  */
+  TDDE_ERR_ARG = -1,      /* bad argument or shape; nothing was launched                        */
+  TDDE_ERR_HIP = -2,      /* a HIP call failed; message in tdde_last_error                      */
+  TDDE_ERR_NOMEM = -3,    /* device allocation failed in tdde_assemble                          */
+  TDDE_ERR_STATE = -4     /* call order violated (e.g. solve before assemble / set_dt)          */
+} tdde_status;
+
+typedef struct { double re, im; } tdde_c128;
+
+typedef struct tdde_ctx tdde_ctx; /* opaque; use one context per stream / host thread */
+
+typedef struct {
+  int32_t nr;        /* radial functions per component (B-spline count after boundary trim) */
+  int32_t nang;      /* angular channels (kappa, mu)                                         */
+  int32_t half_band; /* radial half-bandwidth hb (order-7 B-splines: 6)                      */
+  int32_t batch;     /* independent instances sharing the operator (different fields)        */
+  int32_t n_fields;  /* time functions per instance                                          */
+} tdde_dims;
+
+/* Operator description (host pointers, copied by tdde_assemble; the caller keeps ownership).
+ * Restates eq. fullH:  H0 block j = sum_n kappa_j^n h_poly[n] (+ h_chan[j]),
+ *                      S block j = sum_n kappa_j^n s_poly[n] (identity when n_s = 0),
+ *                      V_m = (K^a A_m K^b) (x) R_m with K = diag(kappa). */
+typedef struct {
+  const double* kappa;      /* [nang]                                                        */
+  int32_t n_h;              /* number of kappa-polynomial H0 terms (0..4)                    */
+  const double* h_poly;     /* [n_h][2][2][2hb+1][nr] real, or NULL when n_h == 0            */
+  const double* h_chan;     /* [nang][2][2][2hb+1][nr] complex (re, im pairs) or NULL        */
+  int32_t n_s;              /* number of kappa-polynomial S terms (0 = identity, 1..3)       */
+  const double* s_poly;     /* [n_s][2][2][2hb+1][nr] real, or NULL                          */
+  int32_t n_terms;          /* coupling terms                                                */
+  const int32_t* a_rowptr;  /* [n_terms][nang+1] CSR row pointers, offsets into a_col/a_val  */
+                            /* counted from the start of each term's own slice               */
+  const int64_t* a_off;     /* [n_terms+1] start of each term's slice in a_col / a_val       */
+  const int32_t* a_col;     /* concatenated CSR column indices (channels)                    */
+  const double* a_val;      /* concatenated CSR values (real)                                */
+  const double* r_band;     /* [n_terms][2][2][2hb+1][nr] real radial bands                  */
+  const int32_t* kpow;      /* [n_terms][2] exponents (a, b) of K^a A_m K^b                  */
+  const double* coef;       /* [n_terms][2] complex prefactor coef_m                         */
+  const int32_t* field;     /* [n_terms] index of the time function f multiplying term m     */
+} tdde_operator_desc;
+
+/* One time function: f(t) = amp * env(t) * sin(omega t + phase) for 0 < t < T, else 0;
+ * env = sin^2(pi t / T) when envelope != 0, else 1 (eq. ndpPot in the dipole limit; a cosine
+ * factor of eq. bdpA is phase = pi/2). */
+typedef struct {
+  double amp, T, omega, phase;
+  int32_t envelope, pad_;
+} tdde_pulse;
+
+enum { TDDE_GUESS_ZERO = 0, TDDE_GUESS_PREV = 1, TDDE_GUESS_GIVEN = 2 };
+enum { TDDE_PREC_FP64 = 0, TDDE_PREC_MIXED = 1 };
+
+typedef struct {
+  double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2 (recursive, then true residual) */
+  int32_t max_iter;    /* BiCGSTAB iterations per solve (per inner solve in mixed mode)           */
+  int32_t guess;       /* TDDE_GUESS_*                                                            */
+  int32_t precond;     /* 0 = none, 1 = block-diagonal LU of M = S + i dt/2 H0 (eq. matrixM)      */
+  int32_t precision;   /* TDDE_PREC_FP64, or TDDE_PREC_MIXED: FP64 iterative refinement around an */
+                       /* FP32 (complex64) BiCGSTAB; residuals, dots and corrections in FP64       */
+  double inner_tol;    /* mixed only: relative tolerance of each FP32 inner solve (e.g. 1e-5)     */
+  int32_t max_outer;   /* mixed only: refinement steps                                            */
+  int32_t pad_;
+} tdde_solve_opts;
+
+/* Per-instance statistics of one solve / step. */
+typedef struct {
+  int32_t status;       /* tdde_status of this instance                                       */
+  int32_t iters;        /* BiCGSTAB iterations (a converged half iteration counts as one)     */
+  int32_t matvecs;      /* operator applications, residual checks included                     */
+  int32_t restarts;     /* breakdown or failed true-residual restarts                          */
+  int32_t outer_iters;  /* refinement steps (mixed precision), else 0                          */
+  int32_t pad_;
+  double rel_res;       /* recursive residual at exit / ||b||                                  */
+  double true_rel_res;  /* ||b - A x|| / ||b|| at exit                                         */
+} tdde_solve_stats;
+
+/* Create a context for the given sizes on `hip_stream` (hipStream_t or NULL). Allocates nothing
+ * on the device. Errors: TDDE_ERR_ARG for nonpositive sizes or half_band > 8. */
+tdde_status tdde_create(const tdde_dims* dims, void* hip_stream, tdde_ctx** out);
+
+/* Copy the operator to the device (FP64 and FP32 copies) and allocate every workspace buffer.
+ * May be called once per context. Errors: TDDE_ERR_ARG (inconsistent CSR, kappa exponents with
+ * zero kappa, field index out of range), TDDE_ERR_NOMEM, TDDE_ERR_HIP. */
+tdde_status tdde_assemble(tdde_ctx* ctx, const tdde_operator_desc* desc);
+
+/* Set the time step. Factors M = S + i dt/2 H0 per distinct channel block (banded LU without
+ * pivoting, valid because the Hermitian part of M is the SPD overlap S) and uploads the
+ * factors. Must follow tdde_assemble. */
+tdde_status tdde_set_dt(tdde_ctx* ctx, double dt);
+
+/* Pulses of every instance: host array [batch][n_fields]. Used by tdde_step / tdde_run_batched,
+ * which evaluate f at the midpoint time of each step on the device. */
+tdde_status tdde_set_pulses(tdde_ctx* ctx, const tdde_pulse* pulses);
+
+/* Explicit field values f[batch][n_fields] (host) used by tdde_apply and tdde_solve. */
+tdde_status tdde_set_field(tdde_ctx* ctx, const double* f);
+
+/* y = a_s * S x + a_h * H x for every instance, with the fields of tdde_set_field.
+ * x, y: device [batch][nang][2][nr] complex128, x != y. */
+tdde_status tdde_apply(tdde_ctx* ctx, tdde_c128 a_s, tdde_c128 a_h, const void* x_dev, void* y_dev);
+
+/* Same in complex64 with the FP32 operator copy (FP32 accumulation). */
+tdde_status tdde_apply_c64(tdde_ctx* ctx, tdde_c128 a_s, tdde_c128 a_h, const void* x_dev, void* y_dev);
+
+/* Apply the block preconditioner: z = M^-1 v (complex128, device). Needs tdde_set_dt. */
+tdde_status tdde_precond_apply(tdde_ctx* ctx, const void* v_dev, void* z_dev);
+
+/* Solve (S + i dt/2 H) x = b with the fields of tdde_set_field. b, x: device complex128
+ * [batch][nang][2][nr]; x holds the initial guess on entry (opts->guess must be GIVEN or ZERO)
+ * and the solution on exit. stats: host array [batch] or NULL (NULL = no synchronisation).
+ * Returns TDDE_NOT_CONVERGED / TDDE_BREAKDOWN when any instance did not converge. */
+tdde_status tdde_solve(tdde_ctx* ctx, const void* b_dev, void* x_dev, const tdde_solve_opts* opts,
+                       tdde_solve_stats* stats);
+
+/* One time step of every instance from time t: evaluates f_m(t + dt/2) from the pulses, forms
+ * b = (S - i dt/2 H) psi, solves with BiCGSTAB from the chosen guess, writes psi_{n+1} into psi.
+ * guess_dev: device complex128 guess when opts->guess == GIVEN, else ignored (may be NULL).
+ * stats: host [batch] or NULL. */
+tdde_status tdde_step(tdde_ctx* ctx, void* psi_dev, double t, const void* guess_dev, const tdde_solve_opts* opts,
+                      tdde_solve_stats* stats);
+
+/* Advance every instance by up to n_chunk steps in one persistent launch. Instance b advances
+ * from step index step0 while step < n_steps[b] (host array [batch]); time t = t0 + step * dt.
+ * stats_dev: device array [n_chunk][batch] of tdde_solve_stats, or NULL. No host synchronisation. */
+tdde_status tdde_run_batched(tdde_ctx* ctx, void* psi_dev, double t0, int32_t step0, int32_t n_chunk,
+                             const int32_t* n_steps, const tdde_solve_opts* opts, void* stats_dev);
+
+/* Release every device buffer of the context. Accepts NULL. */
+tdde_status tdde_destroy(tdde_ctx* ctx);
+
+/* Persistent-grid size actually used (work-groups) and the per-instance work-group count. */
+tdde_status tdde_launch_info(tdde_ctx* ctx, int32_t* n_wg, int32_t* wg_per_instance);
+
+const char* tdde_status_string(tdde_status s);
+const char* tdde_last_error(const tdde_ctx* ctx); /* NULL ctx: last create error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDDE_H */

@@ -1,0 +1,282 @@
+"""ctypes binding of libtdde.so (include/tdde.h). Argument marshalling only.
+
+Device buffers are torch tensors on the GPU (complex128 / complex64, contiguous); the library
+only sees their data pointers. The library must be built (``python -m paper_2512_21697_amd.build``);
+importing this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdde.so")
+
+TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN = 0, 1, 2
+GUESS_ZERO, GUESS_PREV, GUESS_GIVEN = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+
+class Dims(C.Structure):
+    _fields_ = [("nr", C.c_int32), ("nang", C.c_int32), ("half_band", C.c_int32), ("batch", C.c_int32),
+                ("n_fields", C.c_int32)]
+
+
+class OperatorDescC(C.Structure):
+    _fields_ = [("kappa", C.c_void_p), ("n_h", C.c_int32), ("h_poly", C.c_void_p), ("h_chan", C.c_void_p),
+                ("n_s", C.c_int32), ("s_poly", C.c_void_p), ("n_terms", C.c_int32), ("a_rowptr", C.c_void_p),
+                ("a_off", C.c_void_p), ("a_col", C.c_void_p), ("a_val", C.c_void_p), ("r_band", C.c_void_p),
+                ("kpow", C.c_void_p), ("coef", C.c_void_p), ("field", C.c_void_p)]
+
+
+class PulseC(C.Structure):
+    _fields_ = [("amp", C.c_double), ("T", C.c_double), ("omega", C.c_double), ("phase", C.c_double),
+                ("envelope", C.c_int32), ("pad_", C.c_int32)]
+
+
+class C128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("guess", C.c_int32), ("precond", C.c_int32),
+                ("precision", C.c_int32), ("inner_tol", C.c_double), ("max_outer", C.c_int32), ("pad_", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("matvecs", C.c_int32), ("restarts", C.c_int32),
+                ("outer_iters", C.c_int32), ("pad_", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+
+
+STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"), ("restarts", "<i4"),
+                        ("outer_iters", "<i4"), ("pad_", "<i4"), ("rel_res", "<f8"), ("true_rel_res", "<f8")])
+
+EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field", "tdde_apply",
+           "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_step", "tdde_run_batched", "tdde_destroy",
+           "tdde_launch_info", "tdde_status_string", "tdde_last_error"]
+
+_lib = None
+
+
+def load():
+    """Load libtdde.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2512_21697_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "tdde_create": [C.POINTER(Dims), P, C.POINTER(P)],
+        "tdde_assemble": [P, C.POINTER(OperatorDescC)],
+        "tdde_set_dt": [P, C.c_double],
+        "tdde_set_pulses": [P, P],
+        "tdde_set_field": [P, P],
+        "tdde_apply": [P, C128, C128, P, P],
+        "tdde_apply_c64": [P, C128, C128, P, P],
+        "tdde_precond_apply": [P, P, P],
+        "tdde_solve": [P, P, P, C.POINTER(SolveOpts), P],
+        "tdde_step": [P, P, C.c_double, P, C.POINTER(SolveOpts), P],
+        "tdde_run_batched": [P, P, C.c_double, C.c_int32, C.c_int32, P, C.POINTER(SolveOpts), P],
+        "tdde_destroy": [P],
+        "tdde_launch_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.tdde_status_string.argtypes = [C.c_int]
+    lib.tdde_status_string.restype = C.c_char_p
+    lib.tdde_last_error.argtypes = [P]
+    lib.tdde_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class TddeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tdde status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _buf(t, n, c64=False):
+    """Pointer of a device state buffer after checking dtype, device and element count."""
+    import torch
+    want = torch.complex64 if c64 else torch.complex128
+    if t.dtype != want or not t.is_cuda or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous CUDA {want} tensor with {n} elements, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def solve_opts(tol=1e-12, max_iter=500, guess=GUESS_PREV, precond=0, precision=PREC_FP64, inner_tol=1e-5,
+               max_outer=20):
+    return SolveOpts(tol, max_iter, guess, precond, precision, inner_tol, max_outer, 0)
+
+
+class Solver:
+    """One library context: operator, workspace, stream."""
+
+    def __init__(self, op, batch: int, stream=None):
+        import torch
+        self.lib = load()
+        self.op = op
+        self.batch = batch
+        self.nr, self.nang, self.hb = op.nr, op.nang, op.hb
+        self.n_fields = op.n_fields
+        self.E = op.nang * 2 * op.nr
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        d = Dims(op.nr, op.nang, op.hb, batch, op.n_fields)
+        h = C.c_void_p()
+        st = self.lib.tdde_create(C.byref(d), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != TDDE_OK:
+            raise TddeError(st, self.lib.tdde_last_error(None).decode())
+        self.h = h
+        self._assemble(op)
+
+    def _check(self, st, allow=(TDDE_OK,)):
+        if st not in allow:
+            raise TddeError(st, self.lib.tdde_last_error(self.h).decode())
+        return st
+
+    def _assemble(self, op):
+        keep = []
+
+        def arr(a, dtype):
+            x = _np(a, dtype)
+            keep.append(x)
+            return x.ctypes.data_as(C.c_void_p)
+
+        nr, nang, nb = op.nr, op.nang, 2 * op.hb + 1
+
+        def need(a, shape, what):
+            if tuple(np.shape(a)) != tuple(shape):
+                raise ValueError(f"{what}: expected shape {tuple(shape)}, got {tuple(np.shape(a))}")
+        need(op.kappa, (nang,), "kappa")
+        need(op.h_poly, (op.h_poly.shape[0], 2, 2, nb, nr), "h_poly")
+        need(op.s_poly, (op.s_poly.shape[0], 2, 2, nb, nr), "s_poly")
+        if op.h_chan is not None:
+            need(op.h_chan, (nang, 2, 2, nb, nr), "h_chan")
+        for m, t in enumerate(op.terms):
+            need(t.a_rowptr, (nang + 1,), f"term {m} a_rowptr")
+            need(t.r_band, (2, 2, nb, nr), f"term {m} r_band")
+            if len(t.a_col) != len(t.a_val) or int(t.a_rowptr[-1]) != len(t.a_col):
+                raise ValueError(f"term {m}: CSR arrays inconsistent")
+            if not 0 <= t.field < op.n_fields:
+                raise ValueError(f"term {m}: field index out of range")
+        desc = OperatorDescC()
+        desc.kappa = arr(op.kappa, np.float64)
+        desc.n_h = op.h_poly.shape[0]
+        desc.h_poly = arr(op.h_poly, np.float64) if desc.n_h else None
+        if op.h_chan is not None:
+            hc = np.ascontiguousarray(op.h_chan, dtype=np.complex128).view(np.float64)
+            desc.h_chan = arr(hc, np.float64)
+        desc.n_s = op.s_poly.shape[0]
+        desc.s_poly = arr(op.s_poly, np.float64) if desc.n_s else None
+        T = len(op.terms)
+        desc.n_terms = T
+        if T:
+            rowptr = np.concatenate([t.a_rowptr.astype(np.int32) for t in op.terms])
+            offs = np.zeros(T + 1, dtype=np.int64)
+            offs[1:] = np.cumsum([len(t.a_col) for t in op.terms])
+            desc.a_rowptr = arr(rowptr, np.int32)
+            desc.a_off = arr(offs, np.int64)
+            desc.a_col = arr(np.concatenate([t.a_col for t in op.terms]), np.int32)
+            desc.a_val = arr(np.concatenate([t.a_val for t in op.terms]), np.float64)
+            desc.r_band = arr(np.stack([t.r_band for t in op.terms]), np.float64)
+            desc.kpow = arr(np.array([t.kpow for t in op.terms]), np.int32)
+            desc.coef = arr(np.array([[t.coef.real, t.coef.imag] for t in op.terms]), np.float64)
+            desc.field = arr(np.array([t.field for t in op.terms]), np.int32)
+        self._check(self.lib.tdde_assemble(self.h, C.byref(desc)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tdde_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_dt(self, dt):
+        self._check(self.lib.tdde_set_dt(self.h, float(dt)))
+
+    def set_pulses(self, pulses):
+        arr = (PulseC * (self.batch * self.n_fields))()
+        for b in range(self.batch):
+            for m in range(self.n_fields):
+                p = pulses[b][m]
+                arr[b * self.n_fields + m] = PulseC(p.amp, p.T, p.omega, p.phase, 1 if p.envelope else 0, 0)
+        self._check(self.lib.tdde_set_pulses(self.h, C.cast(arr, C.c_void_p)))
+
+    def set_field(self, f):
+        f = _np(np.asarray(f).reshape(self.batch, self.n_fields), np.float64)
+        self._check(self.lib.tdde_set_field(self.h, f.ctypes.data_as(C.c_void_p)))
+
+    def apply(self, x, y, a_s=1.0, a_h=0.0, c64=False):
+        fn = self.lib.tdde_apply_c64 if c64 else self.lib.tdde_apply
+        n = self.batch * self.E
+        self._check(fn(self.h, C128(complex(a_s).real, complex(a_s).imag), C128(complex(a_h).real, complex(a_h).imag),
+                       _buf(x, n, c64), _buf(y, n, c64)))
+
+    def precond_apply(self, v, z):
+        n = self.batch * self.E
+        self._check(self.lib.tdde_precond_apply(self.h, _buf(v, n), _buf(z, n)))
+
+    def solve(self, b, x, opts, stats=True):
+        out = (SolveStats * self.batch)() if stats else None
+        n = self.batch * self.E
+        st = self._check(self.lib.tdde_solve(self.h, _buf(b, n), _buf(x, n), C.byref(opts),
+                                             C.cast(out, C.c_void_p) if stats else None),
+                         allow=(TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN))
+        return st, ([s.as_dict() for s in out] if stats else None)
+
+    def step(self, psi, t, opts, guess=None, stats=True):
+        out = (SolveStats * self.batch)() if stats else None
+        n = self.batch * self.E
+        g = _buf(guess, n) if guess is not None else None
+        st = self._check(self.lib.tdde_step(self.h, _buf(psi, n), float(t), g, C.byref(opts),
+                                            C.cast(out, C.c_void_p) if stats else None),
+                         allow=(TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN))
+        return st, ([s.as_dict() for s in out] if stats else None)
+
+    def run_batched(self, psi, t0, step0, n_chunk, n_steps, opts, stats_dev=None):
+        ns = _np(n_steps, np.int32)
+        if ns.shape != (self.batch,):
+            raise ValueError("n_steps must have one entry per instance")
+        if stats_dev is not None:
+            import torch
+            if (stats_dev.dtype != torch.uint8 or not stats_dev.is_cuda or not stats_dev.is_contiguous()
+                    or stats_dev.numel() < n_chunk * self.batch * STATS_DTYPE.itemsize):
+                raise ValueError("stats_dev must be a contiguous CUDA uint8 tensor of n_chunk*batch*40 bytes")
+        self._check(self.lib.tdde_run_batched(self.h, _buf(psi, self.batch * self.E), float(t0), int(step0),
+                                              int(n_chunk), ns.ctypes.data_as(C.c_void_p), C.byref(opts),
+                                              _ptr(stats_dev)))
+
+    def launch_info(self):
+        a, b = C.c_int32(), C.c_int32()
+        self._check(self.lib.tdde_launch_info(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value

@@ -1,0 +1,123 @@
+// Matrix-free apply of S and H(t) on one (instance, channel, radial tile) of x[b][j][s][i].
+//
+// eq. fullH: (H x)[j][s][i] = sum_{s',d} H0_j[s][s'][d][i] x[j][s'][i+d]
+//                           + sum_m coef_m f_m sum_{j'} (K^a A_m K^b)[j][j'] sum_{s',d} R_m[s][s'][d][i] x[j'][s'][i+d]
+// with H0_j = sum_n kappa_j^n h_n (+ per-channel complex band), S_j = sum_n kappa_j^n s_n or I.
+//
+// Work-group layout: 256 threads = 2 components x 128 radial points; thread (s, ii) owns
+// y[j][s][i0 + ii]. The x tile of channel j (with a halo of hb points) is staged in LDS; for
+// each coupling term the angular combination w = sum_j' A[j][j'] x[j'] is staged in LDS once
+// per tile, so the radial band contraction reads LDS and the angular gather is not repeated
+// per radial tap.
+#pragma once
+#include "common.hpp"
+
+namespace tdde {
+
+template <typename T> struct TileLds {
+  c2_t<T> xs[2][kHalo];
+  c2_t<T> ws[2][kHalo];
+};
+
+// Stage v[s'][i0-hb .. i0+kTileR+hb) of one channel into dst (zero outside [0, nr)).
+template <typename T>
+__device__ inline void stage_channel(c2_t<T> (*dst)[kHalo], const c2_t<T>* __restrict__ chan, int i0, int nr, int hb) {
+  const int w = kTileR + 2 * hb;
+  for (int k = threadIdx.x; k < 2 * w; k += kThreads) {
+    const int s = k / w, kk = k - s * w, gi = i0 - hb + kk;
+    c2_t<T> v = cmk<T>(0, 0);
+    if (gi >= 0 && gi < nr) v = chan[(size_t)s * nr + gi];
+    dst[s][kk] = v;
+  }
+}
+
+// Stage w[s'][.] = sum_p val[p] * x[col[p]][s'][.] for the CSR row [p0, p1).
+template <typename T>
+__device__ inline void stage_gather(c2_t<T> (*dst)[kHalo], const c2_t<T>* __restrict__ xinst, const int* __restrict__ col,
+                                    const T* __restrict__ val, int p0, int p1, int i0, int nr, int hb) {
+  const int w = kTileR + 2 * hb;
+  const size_t cstride = (size_t)2 * nr;
+  for (int k = threadIdx.x; k < 2 * w; k += kThreads) {
+    const int s = k / w, kk = k - s * w, gi = i0 - hb + kk;
+    c2_t<T> acc = cmk<T>(0, 0);
+    if (gi >= 0 && gi < nr) {
+      for (int p = p0; p < p1; ++p) acc = rfma<T>(val[p], xinst[(size_t)col[p] * cstride + (size_t)s * nr + gi], acc);
+    }
+    dst[s][kk] = acc;
+  }
+}
+
+// Result of one tile apply for the calling thread: S x and H x at (j, s, i).
+template <typename T> struct SH { c2_t<T> sx, hx; };
+
+// coef_f: LDS array [n_terms] of coef_m * f_{field_m}(t) for this instance.
+template <typename T>
+__device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict__ xinst, int j, int i0,
+                                   const double2* coef_f, TileLds<T>& L) {
+  const int nr = op.nr, hb = op.hb, nb = op.nb;
+  const int s = threadIdx.x / kTileR, ii = threadIdx.x - s * kTileR, i = i0 + ii;
+  const bool live = i < nr;
+  const size_t cstride = (size_t)2 * nr;
+  SH<T> out;
+  out.sx = cmk<T>(0, 0);
+  out.hx = cmk<T>(0, 0);
+
+  __syncthreads();
+  stage_channel<T>(L.xs, xinst + (size_t)j * cstride, i0, nr, hb);
+  __syncthreads();
+
+  const T kap = op.kappa[j];
+  if (live) {
+    const size_t bstride = (size_t)nb * nr;
+    // H0 (kappa polynomial, Horner) and S
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const bool do_h = op.n_h > 0 && (op.pq_h || s2 == s);
+      const bool do_c = op.has_chan && (op.pq_chan || s2 == s);
+      const bool do_s = op.n_s > 0 && (op.pq_s || s2 == s);
+      if (!(do_h || do_c || do_s)) continue;
+      const size_t blk = (size_t)(s * 2 + s2) * bstride;
+      for (int d = -hb; d <= hb; ++d) {
+        const c2_t<T> xv = L.xs[s2][ii + hb + d];
+        const size_t off = blk + (size_t)(d + hb) * nr + i;
+        if (do_h) {
+          T tap = op.h_poly[(size_t)(op.n_h - 1) * 4 * bstride + off];
+          for (int n = op.n_h - 2; n >= 0; --n) tap = fma(tap, kap, op.h_poly[(size_t)n * 4 * bstride + off]);
+          out.hx = rfma<T>(tap, xv, out.hx);
+        }
+        if (do_c) out.hx = cfma<T>(op.h_chan[(size_t)j * 4 * bstride + off], xv, out.hx);
+        if (do_s) {
+          T tap = op.s_poly[(size_t)(op.n_s - 1) * 4 * bstride + off];
+          for (int n = op.n_s - 2; n >= 0; --n) tap = fma(tap, kap, op.s_poly[(size_t)n * 4 * bstride + off]);
+          out.sx = rfma<T>(tap, xv, out.sx);
+        }
+      }
+    }
+    if (op.n_s == 0) out.sx = L.xs[s][ii + hb];
+  }
+
+  // coupling terms: stage the angular combination, then the radial band contraction
+  for (int m = 0; m < op.n_terms; ++m) {
+    const int* rp = op.t_rowptr + (size_t)m * (op.nang + 1);
+    const int p0 = rp[j], p1 = rp[j + 1];
+    const double2 cf = coef_f[m];
+    if (p0 == p1 || (cf.x == 0.0 && cf.y == 0.0)) continue;  // uniform over the work-group
+    __syncthreads();
+    stage_gather<T>(L.ws, xinst, op.t_col, op.t_val, p0, p1, i0, nr, hb);
+    __syncthreads();
+    if (live) {
+      const size_t bstride = (size_t)nb * nr;
+      const T* R = op.t_r + (size_t)m * 4 * bstride;
+      const bool pq = op.t_pq[m] != 0;
+      c2_t<T> acc = cmk<T>(0, 0);
+      for (int s2 = 0; s2 < 2; ++s2) {
+        if (!pq && s2 != s) continue;
+        const T* Rb = R + (size_t)(s * 2 + s2) * bstride + i;
+        for (int d = -hb; d <= hb; ++d) acc = rfma<T>(Rb[(size_t)(d + hb) * nr], L.ws[s2][ii + hb + d], acc);
+      }
+      out.hx = cfma<T>(cmk<T>((T)cf.x, (T)cf.y), acc, out.hx);
+    }
+  }
+  return out;
+}
+
+}  // namespace tdde

@@ -1,0 +1,603 @@
+// Persistent BiCGSTAB for the Crank-Nicolson step (eq. solPsi), all instances of a batch in one
+// cooperative launch.
+//
+// Grid: n_wg co-resident work-groups; instance b owns work-groups [b*G, (b+1)*G). Tiles
+// (channel j, radial tile) of an instance are dealt round-robin to its G work-groups, so tile k
+// runs on XCD (b*G + k % G) % 8: for G a multiple of 8 the same tile of every instance shares
+// one L2 (operator bands are reused across instances), and for one instance all channels of a
+// radial tile share one L2 (angular gathers hit in L2).
+//
+// Reductions are deterministic: every work-group writes one partial per dot product, and after
+// the grid barrier every work-group of the instance sums the G partials in the same order.
+// Each BiCGSTAB iteration (van der Vorst 1992; right preconditioner K = M of eq. matrixM when
+// enabled) runs in five windows separated by grid barriers:
+//   W0  rho, ||r|| -> convergence / restart decision, beta;  p = r + beta (p - omega v), p^ = K^-1 p
+//   W1  v = A p^, <r^, v>              (VERIFY instances: r = b - A x, ||r||)
+//   W2  alpha;  s = r - alpha v, s^ = K^-1 s, ||s||   (VERIFY: accept or restart)
+//   W3  ||s|| test (half step);  t = A s^, <t, s>, <t, t>
+//   W4  omega;  x += alpha p^ + omega s^,  r = s - omega t,  <r^, r>, ||r||
+// The loop ends when the count of unfinished instances, read right after the W1 barrier, is zero.
+#pragma once
+#include "apply.hpp"
+#include "precond.hpp"
+
+namespace tdde {
+
+enum { ST_INACTIVE = 0, ST_ACTIVE = 1, ST_VERIFY = 2, ST_DONE = 3, ST_FAILED = 4, ST_PENDING = 5, ST_BREAKDOWN = 6 };
+// A slot is never read and written in the same barrier window by one instance.
+//   RHO, RR: written W4 (and W1 for VERIFY), read W0 (RR also W2 for VERIFY)
+//   AUX: ||r||^2 of a restart, written W0/W1/W2, read W0 when PENDING
+//   ORR, OBB: outer refinement residual / rhs norms (mixed precision)
+enum { SLOT_RHO = 0, SLOT_RR, SLOT_RV, SLOT_SS, SLOT_TS, SLOT_TT, SLOT_BB, SLOT_AUX, SLOT_ORR, SLOT_OBB, kSlots };
+enum { GUESS_ZERO = 0, GUESS_PREV = 1, GUESS_GIVEN = 2 };
+enum { MODE_SOLVE = 0, MODE_STEP = 1 };
+
+struct StatsDev {
+  int status, iters, matvecs, restarts, outer_iters, pad;
+  double rel_res, true_rel_res;
+};
+
+template <typename T> struct KVec {
+  c2_t<T> *x, *r, *rh, *p, *ph, *v, *s, *sh, *t;
+};
+
+struct SolveArgs {
+  DevOp<double> op64;
+  DevOp<float> op32;
+  DevPrec<double> pc64;
+  DevPrec<float> pc32;
+  KVec<double> v64;
+  KVec<float> v32;
+  double2* bvec;          // right-hand side workspace (FP64)
+  double2* r64;           // outer residual (mixed precision)
+  float2* rhs32;          // inner right-hand side (mixed precision)
+  int B, G, E, n_wg;
+  int mode, guess, use_prec, mixed;
+  int max_iter, max_outer;
+  double tol, inner_tol, dt, t0;
+  int step0, n_chunk, n_fields, pad0;
+  const int* n_steps;     // device [B] or null
+  const PulseDev* pulses; // device [B][n_fields]
+  const double* fvals;    // device [B][n_fields]
+  double2* psi;           // MODE_STEP state (in/out)
+  const double2* guess_in;
+  const double2* b_in;    // MODE_SOLVE right-hand side
+  double2* x_io;          // MODE_SOLVE solution (in: guess)
+  double2* part;          // [B][G][kSlots]
+  unsigned* bar;          // grid barrier state
+  int* counters;          // [n_chunk][kCounterPerStep]
+  StatsDev* stats;        // [n_chunk][B] or null
+};
+constexpr int kCounterPerStep = 64;
+
+struct WgInfo {
+  int b, g, G, live;
+};
+
+struct Inst {
+  int state, fresh, iters, matvecs, restarts, first;
+  double2 rho, alpha, omega;
+  double bb, target2, rel_res, true_rel_res;
+};
+
+template <typename T> union SharedLds {
+  TileLds<T> tile;
+  c2_t<T> chain[kMaxSeg * kPrecW];
+};
+
+struct Shared {
+  union {
+    SharedLds<double> d;
+    SharedLds<float> f;
+  } u;
+  double red[kThreads / 64];
+  double2 coef_f[kMaxTerms];
+};
+
+__device__ inline void put_partial(const SolveArgs& a, const WgInfo& wi, int slot, double2 v, Shared& sh) {
+  const double2 s = wg_sum2(v, sh.red);
+  if (threadIdx.x == 0) a.part[((size_t)wi.b * wi.G + wi.g) * kSlots + slot] = s;
+}
+__device__ inline double2 get_total(const SolveArgs& a, const WgInfo& wi, int slot, Shared& sh) {
+  double2 acc = make_double2(0.0, 0.0);
+  for (int gg = threadIdx.x; gg < wi.G; gg += kThreads) {
+    const double2 v = a.part[((size_t)wi.b * wi.G + gg) * kSlots + slot];
+    acc.x += v.x; acc.y += v.y;
+  }
+  return wg_sum2(acc, sh.red);
+}
+
+__device__ inline void counter_add(int* c, int v) {
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(c, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T> __device__ inline const DevOp<T>& op_of(const SolveArgs& a);
+template <> __device__ inline const DevOp<double>& op_of<double>(const SolveArgs& a) { return a.op64; }
+template <> __device__ inline const DevOp<float>& op_of<float>(const SolveArgs& a) { return a.op32; }
+template <typename T> __device__ inline const DevPrec<T>& pc_of(const SolveArgs& a);
+template <> __device__ inline const DevPrec<double>& pc_of<double>(const SolveArgs& a) { return a.pc64; }
+template <> __device__ inline const DevPrec<float>& pc_of<float>(const SolveArgs& a) { return a.pc32; }
+template <typename T> __device__ inline SharedLds<T>& lds_of(Shared& sh);
+template <> __device__ inline SharedLds<double>& lds_of<double>(Shared& sh) { return sh.u.d; }
+template <> __device__ inline SharedLds<float>& lds_of<float>(Shared& sh) { return sh.u.f; }
+
+// Tile loop of the calling work-group over its instance.
+#define FOR_TILES(op, wi)                                                          \
+  for (int tile_ = (wi).g; tile_ < (op).nang * (op).n_itiles; tile_ += (wi).G)     \
+    for (int j_ = tile_ / (op).n_itiles, once_ = 1; once_; once_ = 0)             \
+      for (int i0_ = (tile_ - j_ * (op).n_itiles) * kTileR, once2_ = 1; once2_; once2_ = 0)
+
+// Element owned by the calling thread in tile (j, i0); -1 when past nr.
+template <typename T> __device__ inline long tile_elem(const DevOp<T>& op, int j, int i0) {
+  const int s = threadIdx.x / kTileR, i = i0 + (threadIdx.x - s * kTileR);
+  return i < op.nr ? (long)j * 2 * op.nr + (long)s * op.nr + i : -1;
+}
+
+// Chain loop: channel j of the instance handled by wave 0 of work-group (j % G).
+#define FOR_CHAINS(op, wi) for (int j_ = (wi).g; j_ < (op).nang; j_ += (wi).G)
+
+template <typename T>
+__device__ inline c2_t<T> load_c(const c2_t<T>* p, long e) { return p[e]; }
+
+// y = S x + ah * H x for own tiles of instance b (A of the step), with optional fused outputs.
+// The caller supplies a functor on (element, S x, H x).
+template <typename T, typename F>
+__device__ inline void apply_own(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
+  const DevOp<T>& op = op_of<T>(a);
+  FOR_TILES(op, wi) {
+    SH<T> r = apply_tile<T>(op, xin, j_, i0_, sh.coef_f, lds_of<T>(sh).tile);
+    const long e = tile_elem<T>(op, j_, i0_);
+    if (e >= 0) f(e, r.sx, r.hx);
+  }
+}
+
+template <typename T, typename F>
+__device__ inline void elem_own(const SolveArgs& a, const WgInfo& wi, F&& f) {
+  const DevOp<T>& op = op_of<T>(a);
+  FOR_TILES(op, wi) {
+    const long e = tile_elem<T>(op, j_, i0_);
+    if (e >= 0) f(e);
+  }
+}
+
+template <typename T> __device__ inline c2_t<T> to_c(double2 z) { return cmk<T>((T)z.x, (T)z.y); }
+
+__device__ inline double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ inline double2 dmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+
+// Preconditioner chain phase for own channels: mode MODE_P / MODE_FRESH / MODE_S.
+template <typename T>
+__device__ inline double chains_own(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, size_t base, int mode,
+                                    double2 c1, double2 c2, Shared& sh) {
+  const DevOp<T>& op = op_of<T>(a);
+  const DevPrec<T>& pc = pc_of<T>(a);
+  double nrm2 = 0.0;
+  FOR_CHAINS(op, wi) {
+    if (threadIdx.x < 64) {
+      const size_t cb = base + (size_t)j_ * 2 * op.nr;
+      ChainIO<T> io;
+      io.r = V.r + cb;
+      io.v = V.v + cb;
+      io.pz = (mode == MODE_S ? V.s : V.p) + cb;
+      io.out = (mode == MODE_S ? V.sh : V.ph) + cb;
+      io.c1 = c1;
+      io.c2 = c2;
+      io.mode = mode;
+      const double n2 = chain_solve<T>(pc, pc.block_of[j_], op.nr, io, lds_of<T>(sh).chain);
+      if (threadIdx.x == 0) nrm2 += n2;
+    }
+  }
+  return nrm2;  // valid in thread 0
+}
+
+// BiCGSTAB on A y = rhs for every live instance; y holds the initial guess, r = rhs - A y and
+// r^ = r are already written and their partials (SLOT_RHO, SLOT_RR, SLOT_BB) stored; the
+// unfinished-instance counter *cnt already counts this instance. verify: confirm convergence
+// with the true residual (restart on failure).
+template <typename T>
+__device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, const c2_t<T>* rhs, size_t base,
+                              double tol, int max_iter, bool verify, int* cnt, Inst& st, Shared& sh) {
+  const DevOp<T>& op = op_of<T>(a);
+  const double2 ah = make_double2(0.0, 0.5 * a.dt);
+  const c2_t<T> ahc = to_c<T>(ah);
+  const bool prec = a.use_prec != 0;
+  c2_t<T>* x = V.x + base;
+  c2_t<T>* r = V.r + base;
+  c2_t<T>* rh = V.rh + base;
+  c2_t<T>* p = V.p + base;
+  c2_t<T>* ph = V.ph + base;
+  c2_t<T>* v = V.v + base;
+  c2_t<T>* s = V.s + base;
+  c2_t<T>* shv = V.sh + base;
+  c2_t<T>* t = V.t + base;
+  const c2_t<T>* b_ = rhs + base;
+  while (true) {
+    // ---------------- W0
+    if (!grid_barrier(a.bar, a.n_wg)) return;
+    bool work = false;
+    double2 beta = make_double2(0.0, 0.0);
+    if (wi.live && (st.state == ST_ACTIVE || st.state == ST_PENDING)) {
+      const bool pend = st.state == ST_PENDING;
+      const double2 rho = get_total(a, wi, pend ? SLOT_AUX : SLOT_RHO, sh);
+      const double rr = pend ? rho.x : get_total(a, wi, SLOT_RR, sh).x;
+      if (st.first) {
+        st.bb = get_total(a, wi, SLOT_BB, sh).x;
+        st.target2 = tol * tol * st.bb;
+        st.first = 0;
+      }
+      st.rel_res = st.bb > 0 ? sqrt(rr / st.bb) : 0.0;
+      if (st.state == ST_PENDING) { st.state = ST_ACTIVE; st.fresh = 1; }
+      if (rr <= st.target2) {
+        st.state = verify ? ST_VERIFY : ST_DONE;
+        if (!verify) { st.true_rel_res = st.rel_res; counter_add(cnt, -1); }
+      } else if (st.iters >= max_iter) {
+        st.state = ST_FAILED;
+        counter_add(cnt, -1);
+      } else {
+        const double rn = sqrt(rho.x * rho.x + rho.y * rho.y);
+        const double om = sqrt(st.omega.x * st.omega.x + st.omega.y * st.omega.y);
+        if (!st.fresh && (rn <= 1e-300 * (1.0 + rr) || om == 0.0)) {
+          // breakdown: restart with r^ = r
+          st.restarts++;
+          if (st.restarts > 20) {
+            st.state = ST_BREAKDOWN;
+            counter_add(cnt, -1);
+          } else {
+            // restart from the same r with r^ = r; rho of the restart is ||r||^2
+            st.state = ST_PENDING;
+            double2 acc = make_double2(0.0, 0.0);
+            elem_own<T>(a, wi, [&](long e) { rh[e] = r[e]; dot_acc(acc, r[e], r[e]); });
+            put_partial(a, wi, SLOT_AUX, acc, sh);
+          }
+        } else {
+          if (!st.fresh) beta = dmul(cdiv(rho, st.rho), cdiv(st.alpha, st.omega));
+          st.rho = rho;
+          work = true;
+        }
+      }
+    }
+    if (work) {
+      if (prec) {
+        chains_own<T>(a, wi, V, base, st.fresh ? MODE_FRESH : MODE_P, beta, st.omega, sh);
+      } else {
+        const c2_t<T> bc = to_c<T>(beta), oc = to_c<T>(st.omega);
+        const bool fr = st.fresh;
+        elem_own<T>(a, wi, [&](long e) {
+          p[e] = fr ? r[e] : cfma<T>(bc, csub<T>(p[e], cmul<T>(oc, v[e])), r[e]);
+        });
+      }
+      st.fresh = 0;
+    }
+    // ---------------- W1
+    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+    if (wi.live && st.state == ST_ACTIVE) {
+      double2 acc = make_double2(0.0, 0.0);
+      apply_own<T>(a, wi, prec ? ph : p, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        const c2_t<T> vv = cfma<T>(ahc, hx, sx);
+        v[e] = vv;
+        dot_acc(acc, rh[e], vv);
+      });
+      put_partial(a, wi, SLOT_RV, acc, sh);
+      st.matvecs++;
+    } else if (wi.live && st.state == ST_VERIFY) {
+      double2 acc = make_double2(0.0, 0.0);
+      apply_own<T>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        const c2_t<T> rr = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
+        r[e] = rr;
+        dot_acc(acc, rr, rr);
+      });
+      put_partial(a, wi, SLOT_RR, acc, sh);
+      put_partial(a, wi, SLOT_AUX, acc, sh);
+      st.matvecs++;
+    }
+    // ---------------- W2
+    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (wi.live && st.state == ST_ACTIVE) {
+      const double2 rv = get_total(a, wi, SLOT_RV, sh);
+      if (rv.x == 0.0 && rv.y == 0.0) {
+        st.state = ST_PENDING;  // breakdown: restart at the next W0 from the same r
+        st.restarts++;
+        double2 acc = make_double2(0.0, 0.0);
+        elem_own<T>(a, wi, [&](long e) { rh[e] = r[e]; dot_acc(acc, r[e], r[e]); });
+        put_partial(a, wi, SLOT_AUX, acc, sh);
+      } else {
+        st.alpha = cdiv(st.rho, rv);
+        double n2 = 0.0;
+        if (prec) {
+          n2 = chains_own<T>(a, wi, V, base, MODE_S, st.alpha, st.alpha, sh);
+        } else {
+          const c2_t<T> al = to_c<T>(st.alpha);
+          elem_own<T>(a, wi, [&](long e) {
+            const c2_t<T> sv = csub<T>(r[e], cmul<T>(al, v[e]));
+            s[e] = sv;
+            n2 += (double)sv.x * sv.x + (double)sv.y * sv.y;
+          });
+        }
+        put_partial(a, wi, SLOT_SS, make_double2(n2, 0.0), sh);
+      }
+    } else if (wi.live && st.state == ST_VERIFY) {
+      const double rr = get_total(a, wi, SLOT_RR, sh).x;
+      st.true_rel_res = st.bb > 0 ? sqrt(rr / st.bb) : 0.0;
+      if (rr <= st.target2) {
+        st.state = ST_DONE;
+        counter_add(cnt, -1);
+      } else if (st.iters >= max_iter) {
+        st.state = ST_FAILED;
+        counter_add(cnt, -1);
+      } else {
+        st.state = ST_PENDING;  // true residual too large: restart from it (AUX holds ||r||^2)
+        st.restarts++;
+        elem_own<T>(a, wi, [&](long e) { rh[e] = r[e]; });
+      }
+    }
+    // ---------------- W3
+    if (!grid_barrier(a.bar, a.n_wg)) return;
+    bool half_done = false;
+    if (wi.live && st.state == ST_ACTIVE) {
+      const double ss = get_total(a, wi, SLOT_SS, sh).x;
+      if (ss <= st.target2) {
+        const c2_t<T> al = to_c<T>(st.alpha);
+        const c2_t<T>* dir = prec ? ph : p;
+        elem_own<T>(a, wi, [&](long e) { x[e] = cfma<T>(al, dir[e], x[e]); });
+        st.iters++;
+        st.rel_res = st.bb > 0 ? sqrt(ss / st.bb) : 0.0;
+        st.state = verify ? ST_VERIFY : ST_DONE;
+        if (!verify) { st.true_rel_res = st.rel_res; counter_add(cnt, -1); }
+        half_done = true;
+      } else {
+        double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
+        apply_own<T>(a, wi, prec ? shv : s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+          const c2_t<T> tv = cfma<T>(ahc, hx, sx);
+          t[e] = tv;
+          dot_acc(ts, tv, s[e]);
+          dot_acc(tt, tv, tv);
+        });
+        put_partial(a, wi, SLOT_TS, ts, sh);
+        put_partial(a, wi, SLOT_TT, tt, sh);
+        st.matvecs++;
+      }
+    }
+    // ---------------- W4
+    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (wi.live && st.state == ST_ACTIVE && !half_done) {
+      const double2 ts = get_total(a, wi, SLOT_TS, sh);
+      const double tt = get_total(a, wi, SLOT_TT, sh).x;
+      st.omega = tt > 0.0 ? make_double2(ts.x / tt, ts.y / tt) : make_double2(0.0, 0.0);
+      const c2_t<T> al = to_c<T>(st.alpha), om = to_c<T>(st.omega);
+      const c2_t<T>* pd = prec ? ph : p;
+      const c2_t<T>* sd = prec ? shv : s;
+      double2 rho = make_double2(0.0, 0.0), rr = make_double2(0.0, 0.0);
+      elem_own<T>(a, wi, [&](long e) {
+        x[e] = cfma<T>(om, sd[e], cfma<T>(al, pd[e], x[e]));
+        const c2_t<T> rv = csub<T>(s[e], cmul<T>(om, t[e]));
+        r[e] = rv;
+        dot_acc(rho, rh[e], rv);
+        dot_acc(rr, rv, rv);
+      });
+      put_partial(a, wi, SLOT_RHO, rho, sh);
+      put_partial(a, wi, SLOT_RR, rr, sh);
+      st.iters++;
+    }
+  }
+}
+
+__device__ inline void fields_to_lds(const SolveArgs& a, const WgInfo& wi, double t_mid, Shared& sh) {
+  __syncthreads();
+  const DevOp<double>& op = a.op64;
+  if (threadIdx.x < op.n_terms) {
+    const int m = threadIdx.x;
+    double f = 0.0;
+    if (wi.live) {
+      const int fi = op.t_field[m];
+      f = a.mode == MODE_STEP ? pulse_eval(a.pulses[(size_t)wi.b * a.n_fields + fi], t_mid)
+                              : a.fvals[(size_t)wi.b * a.n_fields + fi];
+    }
+    const double2 c = op.t_coef[m];
+    sh.coef_f[m] = make_double2(c.x * f, c.y * f);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
+  __shared__ Shared sh;
+  WgInfo wi;
+  wi.G = a.G;
+  wi.live = blockIdx.x < (unsigned)(a.B * a.G);
+  wi.b = wi.live ? blockIdx.x / a.G : 0;
+  wi.g = wi.live ? blockIdx.x % a.G : 0;
+  const size_t base = (size_t)wi.b * a.E;
+  const double2 ah = make_double2(0.0, 0.5 * a.dt);
+  const c2_t<double> ahc = ah, mahc = make_double2(0.0, -0.5 * a.dt);
+
+  for (int k = 0; k < a.n_chunk; ++k) {
+    const int step = a.step0 + k;
+    int* cnt = a.counters + (size_t)k * kCounterPerStep;
+    if (!grid_barrier(a.bar, a.n_wg)) return;
+    const bool inst = wi.live && (a.mode == MODE_SOLVE || a.n_steps == nullptr || step < a.n_steps[wi.b]);
+    WgInfo wk = wi;
+    wk.live = inst;
+    const double t_mid = a.t0 + (double)step * a.dt + 0.5 * a.dt;
+    fields_to_lds(a, wk, t_mid, sh);
+
+    Inst st = {};
+    st.state = inst ? ST_ACTIVE : ST_INACTIVE;
+    st.fresh = 1;
+    st.first = 1;
+    st.omega = make_double2(1.0, 0.0);
+    st.alpha = make_double2(1.0, 0.0);
+    st.rho = make_double2(1.0, 0.0);
+
+    KVec<double> V = a.v64;
+    double2* x = V.x + base;
+    double2* bv = a.bvec + base;
+    // ---- right-hand side b = (S - i dt/2 H) psi and the initial guess
+    if (inst) {
+      if (a.mode == MODE_STEP) {
+        double2 bb = {0, 0}, rr = {0, 0};
+        const double2* psi = a.psi + base;
+        const int gs = a.guess;
+        const bool direct_r = !a.mixed && gs != GUESS_GIVEN;
+        apply_own<double>(a, wk, psi, sh, [&](long e, double2 sx, double2 hx) {
+          const double2 bval = cfma<double>(mahc, hx, sx);
+          bv[e] = bval;
+          dot_acc(bb, bval, bval);
+          if (gs == GUESS_PREV) x[e] = psi[e];
+          else if (gs == GUESS_ZERO) x[e] = make_double2(0.0, 0.0);
+          else x[e] = a.guess_in[base + e];
+          if (direct_r) {
+            // r = b - A x0: for x0 = psi it is -i dt H psi; for x0 = 0 it is b
+            const double2 rv = gs == GUESS_PREV ? cmul<double>(make_double2(0.0, -a.dt), hx) : bval;
+            V.r[base + e] = rv;
+            V.rh[base + e] = rv;
+            dot_acc(rr, rv, rv);
+          }
+        });
+        put_partial(a, wk, a.mixed ? SLOT_OBB : SLOT_BB, bb, sh);
+        if (direct_r) { put_partial(a, wk, SLOT_RHO, rr, sh); put_partial(a, wk, SLOT_RR, rr, sh); }
+        st.matvecs++;
+      } else {
+        // MODE_SOLVE: copy b and the guess into the workspace
+        double2 bb = {0, 0};
+        elem_own<double>(a, wk, [&](long e) {
+          const double2 bval = a.b_in[base + e];
+          bv[e] = bval;
+          dot_acc(bb, bval, bval);
+          x[e] = a.guess == GUESS_ZERO ? make_double2(0.0, 0.0) : a.x_io[base + e];
+        });
+        put_partial(a, wk, a.mixed ? SLOT_OBB : SLOT_BB, bb, sh);
+      }
+    }
+    const bool need_r = a.mixed || a.guess == GUESS_GIVEN || a.mode == MODE_SOLVE;
+    if (need_r) {
+      // r = b - A x0 in FP64 (the outer residual in mixed precision)
+      if (!grid_barrier(a.bar, a.n_wg)) return;
+      if (inst) {
+        double2 rr = {0, 0};
+        double2* rt = a.mixed ? a.r64 + base : V.r + base;
+        apply_own<double>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
+          const double2 rv = csub<double>(bv[e], cfma<double>(ahc, hx, sx));
+          rt[e] = rv;
+          if (!a.mixed) V.rh[base + e] = rv;
+          dot_acc(rr, rv, rv);
+        });
+        if (!a.mixed) {
+          put_partial(a, wk, SLOT_RHO, rr, sh);
+          put_partial(a, wk, SLOT_RR, rr, sh);
+        } else {
+          put_partial(a, wk, SLOT_ORR, rr, sh);
+        }
+        st.matvecs++;
+      }
+    }
+
+    if (!a.mixed) {
+      if (inst) counter_add(cnt, 1);
+      krylov<double>(a, wk, V, a.bvec, base, a.tol, a.max_iter, true, cnt, st, sh);
+    } else {
+      // ---- FP64 iterative refinement around an FP32 BiCGSTAB (inner residuals, dots in FP64)
+      KVec<float> U = a.v32;
+      int outer_state = inst ? ST_ACTIVE : ST_INACTIVE;
+      int total_iters = 0, total_mv = st.matvecs, outer = 0;
+      double bb = 0.0;
+      int* ocnt = cnt + 1;
+      if (inst) counter_add(ocnt, 1);
+      for (int it = 0;; ++it) {
+        if (!grid_barrier(a.bar, a.n_wg)) return;
+        int* icnt = cnt + 2 + (it % (kCounterPerStep - 2));
+        Inst ist = {};
+        ist.state = ST_INACTIVE;
+        double rnorm = 0.0;
+        if (outer_state == ST_ACTIVE) {
+          const double rr = get_total(a, wk, SLOT_ORR, sh).x;
+          if (it == 0) bb = get_total(a, wk, SLOT_OBB, sh).x;
+          st.rel_res = st.true_rel_res = bb > 0 ? sqrt(rr / bb) : 0.0;
+          if (rr <= a.tol * a.tol * bb) {
+            outer_state = ST_DONE;
+            counter_add(ocnt, -1);
+          } else if (it >= a.max_outer) {
+            outer_state = ST_FAILED;
+            counter_add(ocnt, -1);
+          } else {
+            rnorm = sqrt(rr);
+            const double sc = 1.0 / rnorm;
+            const double2* r64 = a.r64 + base;
+            double2 rho = {0, 0};
+            elem_own<float>(a, wk, [&](long e) {
+              const float2 z = make_float2((float)(r64[e].x * sc), (float)(r64[e].y * sc));
+              a.rhs32[base + e] = z;
+              U.r[base + e] = z;
+              U.rh[base + e] = z;
+              U.x[base + e] = make_float2(0.f, 0.f);
+              dot_acc(rho, z, z);
+            });
+            put_partial(a, wk, SLOT_RHO, rho, sh);
+            put_partial(a, wk, SLOT_RR, rho, sh);
+            put_partial(a, wk, SLOT_BB, rho, sh);
+            ist.state = ST_ACTIVE;
+            ist.fresh = 1;
+            ist.first = 1;
+            ist.omega = ist.alpha = ist.rho = make_double2(1.0, 0.0);
+            counter_add(icnt, 1);
+            outer++;
+          }
+        }
+        if (!grid_barrier(a.bar, a.n_wg)) return;
+        if (__hip_atomic_load(ocnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+        WgInfo wq = wk;
+        wq.live = ist.state == ST_ACTIVE;
+        krylov<float>(a, wq, U, a.rhs32, base, a.inner_tol, a.max_iter, false, icnt, ist, sh);
+        total_iters += ist.iters;
+        total_mv += ist.matvecs;
+        // x += ||r|| d (FP64), then r = b - A x (FP64)
+        if (!grid_barrier(a.bar, a.n_wg)) return;
+        if (wq.live) {
+          const float2* d = U.x + base;
+          elem_own<double>(a, wk, [&](long e) {
+            x[e].x += rnorm * (double)d[e].x;
+            x[e].y += rnorm * (double)d[e].y;
+          });
+        }
+        if (!grid_barrier(a.bar, a.n_wg)) return;
+        if (wq.live) {
+          double2 rr = {0, 0};
+          double2* rt = a.r64 + base;
+          apply_own<double>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
+            const double2 rv = csub<double>(bv[e], cfma<double>(ahc, hx, sx));
+            rt[e] = rv;
+            dot_acc(rr, rv, rv);
+          });
+          put_partial(a, wk, SLOT_ORR, rr, sh);
+          total_mv++;
+        }
+      }
+      st.iters = total_iters;
+      st.matvecs = total_mv;
+      st.state = outer_state == ST_DONE ? ST_DONE : (outer_state == ST_INACTIVE ? ST_INACTIVE : ST_FAILED);
+      st.restarts = outer;  // reported as outer iterations below
+    }
+
+    // ---- write back and statistics
+    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (inst) {
+      double2* dst = a.mode == MODE_STEP ? a.psi + base : a.x_io + base;
+      elem_own<double>(a, wk, [&](long e) { dst[e] = x[e]; });
+      if (a.stats != nullptr && wk.g == 0 && threadIdx.x == 0) {
+        StatsDev& o = a.stats[(size_t)k * a.B + wk.b];
+        o.status = st.state == ST_DONE ? 0 : (st.state == ST_BREAKDOWN ? 2 : 1);
+        o.iters = st.iters;
+        o.matvecs = st.matvecs;
+        o.restarts = a.mixed ? 0 : st.restarts;
+        o.outer_iters = a.mixed ? st.restarts : 0;
+        o.rel_res = st.rel_res;
+        o.true_rel_res = st.true_rel_res;
+      }
+    }
+  }
+  grid_barrier(a.bar, a.n_wg);
+}
+
+}  // namespace tdde

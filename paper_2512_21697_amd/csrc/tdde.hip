@@ -1,0 +1,691 @@
+// Host side of the TDDE library: context, operator upload, preconditioner factorisation and the
+// C ABI declared in include/tdde.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tdde.h"
+#include "solver.hpp"
+
+using namespace tdde;
+using cd = std::complex<double>;
+
+struct tdde_ctx {
+  tdde_dims d{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int E = 0;            // unknowns per instance
+  bool assembled = false;
+  bool dt_set = false;
+  bool field_set = false;
+  bool pulses_set = false;
+  double dt = 0.0;
+  std::vector<void*> allocs;
+  // host copy of what the preconditioner needs
+  std::vector<double> kappa, h_poly, h_chan, s_poly;
+  int n_h = 0, n_s = 0, has_chan = 0;
+  // device operator
+  DevOp<double> op64{};
+  DevOp<float> op32{};
+  DevPrec<double> pc64{};
+  DevPrec<float> pc32{};
+  std::vector<int> block_of;
+  int nblk = 0;
+  bool prec_alloc = false;
+  // workspace
+  KVec<double> v64{};
+  KVec<float> v32{};
+  KVec<double> v64np{};  // aliases without preconditioner (p^ = p, s^ = s)
+  KVec<float> v32np{};
+  double2* bvec = nullptr;
+  double2* r64 = nullptr;
+  float2* rhs32 = nullptr;
+  double2* part = nullptr;
+  unsigned* bar = nullptr;
+  int* counters = nullptr;
+  int n_counters = 0;
+  StatsDev* stats_dev = nullptr;
+  int stats_cap = 0;
+  double* fvals = nullptr;
+  PulseDev* pulses = nullptr;
+  int* n_steps_dev = nullptr;
+  int n_wg = 0, G = 0;
+};
+
+static std::string g_create_err;
+
+#define HIP_TRY(ctx, call)                                                                    \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);                         \
+      return TDDE_ERR_HIP;                                                                    \
+    }                                                                                         \
+  } while (0)
+
+static tdde_status fail(tdde_ctx* c, tdde_status s, const std::string& m) {
+  if (c) c->err = m;
+  return s;
+}
+
+template <typename X> static tdde_status dev_alloc(tdde_ctx* c, X** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(X));
+  if (e != hipSuccess) {
+    c->err = std::string("hipMalloc: ") + hipGetErrorString(e);
+    return TDDE_ERR_NOMEM;
+  }
+  c->allocs.push_back(q);
+  *p = static_cast<X*>(q);
+  return TDDE_OK;
+}
+
+template <typename X> static tdde_status upload(tdde_ctx* c, X** p, const X* h, size_t count) {
+  tdde_status s = dev_alloc(c, p, count);
+  if (s != TDDE_OK) return s;
+  if (count) HIP_TRY(c, hipMemcpy(*p, h, count * sizeof(X), hipMemcpyHostToDevice));
+  return TDDE_OK;
+}
+
+template <typename X> static std::vector<float> to_f32(const X* p, size_t n) {
+  std::vector<float> o(n);
+  for (size_t i = 0; i < n; ++i) o[i] = (float)p[i];
+  return o;
+}
+
+// ------------------------------------------------------------------------------------------ kernels
+
+__global__ void zero_words(unsigned* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void apply_kernel(DevOp<T> op, const c2_t<T>* x, c2_t<T>* y, double2 as,
+                                                         double2 ah, const double* fvals, int n_fields, int E) {
+  __shared__ TileLds<T> L;
+  __shared__ double2 coef_f[kMaxTerms];
+  const int it = blockIdx.x, j = blockIdx.y, b = blockIdx.z;
+  if (threadIdx.x < op.n_terms) {
+    const double f = fvals[(size_t)b * n_fields + op.t_field[threadIdx.x]];
+    const double2 c = op.t_coef[threadIdx.x];
+    coef_f[threadIdx.x] = make_double2(c.x * f, c.y * f);
+  }
+  __syncthreads();
+  const c2_t<T>* xb = x + (size_t)b * E;
+  const int i0 = it * kTileR;
+  SH<T> r = apply_tile<T>(op, xb, j, i0, coef_f, L);
+  const int s = threadIdx.x / kTileR, i = i0 + (threadIdx.x - s * kTileR);
+  if (i < op.nr) {
+    c2_t<T> out = cmul<T>(to_c<T>(as), r.sx);
+    out = cfma<T>(to_c<T>(ah), r.hx, out);
+    y[(size_t)b * E + (size_t)j * 2 * op.nr + (size_t)s * op.nr + i] = out;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void precond_kernel(DevPrec<T> pc, int nr, const c2_t<T>* in, c2_t<T>* out, int E) {
+  __shared__ c2_t<T> lds[kMaxSeg * kPrecW];
+  const int j = blockIdx.x, b = blockIdx.y;
+  const size_t cb = (size_t)b * E + (size_t)j * 2 * nr;
+  ChainIO<T> io;
+  io.r = nullptr;
+  io.v = nullptr;
+  io.pz = const_cast<c2_t<T>*>(in) + cb;
+  io.out = out + cb;
+  io.c1 = io.c2 = make_double2(0, 0);
+  io.mode = MODE_IN;
+  chain_solve<T>(pc, pc.block_of[j], nr, io, lds);
+}
+
+// ------------------------------------------------------------------------------------------ helpers
+
+static int band_index(int hb, int nr, int s, int s2, int d, int i) {
+  return ((s * 2 + s2) * (2 * hb + 1) + (d + hb)) * nr + i;
+}
+
+static bool any_offdiag(const double* bands, int count, int hb, int nr, int stride_complex) {
+  // bands: count blocks of [2][2][nb][nr] (x stride_complex doubles per value)
+  const size_t blk = (size_t)(2 * hb + 1) * nr * stride_complex;
+  for (int c = 0; c < count; ++c)
+    for (int sel = 1; sel <= 2; ++sel) {
+      const double* p = bands + ((size_t)c * 4 + sel) * blk;
+      for (size_t k = 0; k < blk; ++k)
+        if (p[k] != 0.0) return true;
+    }
+  return false;
+}
+
+// ------------------------------------------------------------------------------------------ C ABI
+// (the declarations in tdde.h give every entry point C linkage)
+
+const char* tdde_status_string(tdde_status s) {
+  switch (s) {
+    case TDDE_OK: return "ok";
+    case TDDE_NOT_CONVERGED: return "not converged";
+    case TDDE_BREAKDOWN: return "breakdown";
+    case TDDE_ERR_ARG: return "invalid argument";
+    case TDDE_ERR_HIP: return "HIP error";
+    case TDDE_ERR_NOMEM: return "out of device memory";
+    case TDDE_ERR_STATE: return "invalid call order";
+  }
+  return "unknown status";
+}
+
+const char* tdde_last_error(const tdde_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+tdde_status tdde_create(const tdde_dims* dims, void* hip_stream, tdde_ctx** out) {
+  if (!dims || !out) { g_create_err = "null argument"; return TDDE_ERR_ARG; }
+  *out = nullptr;
+  if (dims->nr <= 0 || dims->nang <= 0 || dims->half_band < 0 || dims->half_band > kMaxHB || dims->batch <= 0 ||
+      dims->n_fields <= 0 || dims->n_fields > kMaxFields) {
+    g_create_err = "dims out of range (nr, nang, batch > 0; 0 <= half_band <= 8; 1 <= n_fields <= 16)";
+    return TDDE_ERR_ARG;
+  }
+  if ((double)dims->nr * dims->nang * 2 > 2.0e9) { g_create_err = "instance too large"; return TDDE_ERR_ARG; }
+  tdde_ctx* c = new tdde_ctx();
+  c->d = *dims;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->E = dims->nang * 2 * dims->nr;
+  *out = c;
+  return TDDE_OK;
+}
+
+tdde_status tdde_destroy(tdde_ctx* ctx) {
+  if (!ctx) return TDDE_OK;
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  delete ctx;
+  return TDDE_OK;
+}
+
+template <typename T>
+static tdde_status build_devop(tdde_ctx* c, const tdde_operator_desc* o, DevOp<T>& op, const std::vector<double>& tval,
+                               const std::vector<int>& rowptr_abs, const std::vector<int>& pq) {
+  const int nr = c->d.nr, nang = c->d.nang, hb = c->d.half_band, nb = 2 * hb + 1;
+  const size_t bsz = (size_t)4 * nb * nr;
+  op.nr = nr; op.nang = nang; op.hb = hb; op.nb = nb;
+  op.n_h = o->n_h; op.n_s = o->n_s; op.has_chan = o->h_chan != nullptr;
+  op.n_terms = o->n_terms;
+  op.n_itiles = (nr + kTileR - 1) / kTileR;
+  op.pq_h = o->n_h > 0 && any_offdiag(o->h_poly, o->n_h, hb, nr, 1);
+  op.pq_s = o->n_s > 0 && any_offdiag(o->s_poly, o->n_s, hb, nr, 1);
+  op.pq_chan = op.has_chan && any_offdiag(o->h_chan, nang, hb, nr, 2);
+  const int64_t nnz = o->n_terms ? o->a_off[o->n_terms] : 0;
+  auto up = [&](auto** dst, const double* src, size_t n) -> tdde_status {
+    using X = std::remove_pointer_t<std::remove_reference_t<decltype(*dst)>>;
+    if constexpr (std::is_same<X, const double>::value || std::is_same<X, double>::value) {
+      return upload(c, (double**)dst, src, n);
+    } else {
+      std::vector<float> f = to_f32(src, n);
+      return upload(c, (float**)dst, f.data(), n);
+    }
+  };
+  tdde_status s;
+  std::vector<double> kap(o->kappa, o->kappa + nang);
+  if ((s = up((T**)&op.kappa, kap.data(), nang)) != TDDE_OK) return s;
+  if ((s = up((T**)&op.h_poly, o->n_h ? o->h_poly : nullptr, (size_t)o->n_h * bsz)) != TDDE_OK) return s;
+  if ((s = up((T**)&op.s_poly, o->n_s ? o->s_poly : nullptr, (size_t)o->n_s * bsz)) != TDDE_OK) return s;
+  if (op.has_chan) {
+    if ((s = up((T**)&op.h_chan, o->h_chan, (size_t)nang * bsz * 2)) != TDDE_OK) return s;
+  } else {
+    op.h_chan = nullptr;
+  }
+  if ((s = upload(c, (int**)&op.t_rowptr, rowptr_abs.data(), rowptr_abs.size())) != TDDE_OK) return s;
+  if ((s = upload(c, (int**)&op.t_col, o->a_col, (size_t)nnz)) != TDDE_OK) return s;
+  if ((s = up((T**)&op.t_val, tval.data(), (size_t)nnz)) != TDDE_OK) return s;
+  if ((s = up((T**)&op.t_r, o->n_terms ? o->r_band : nullptr, (size_t)o->n_terms * bsz)) != TDDE_OK) return s;
+  if ((s = upload(c, (int**)&op.t_pq, pq.data(), pq.size())) != TDDE_OK) return s;
+  if ((s = upload(c, (int**)&op.t_field, o->field, (size_t)o->n_terms)) != TDDE_OK) return s;
+  if ((s = upload(c, (double2**)&op.t_coef, (const double2*)o->coef, (size_t)o->n_terms)) != TDDE_OK) return s;
+  return TDDE_OK;
+}
+
+template <typename T> static tdde_status alloc_kvec(tdde_ctx* c, KVec<T>& V, KVec<T>& Vnp, size_t n) {
+  tdde_status s;
+  c2_t<T>** ptrs[] = {&V.x, &V.r, &V.rh, &V.p, &V.ph, &V.v, &V.s, &V.sh, &V.t};
+  for (auto* p : ptrs)
+    if ((s = dev_alloc(c, p, n)) != TDDE_OK) return s;
+  Vnp = V;
+  Vnp.ph = V.p;
+  Vnp.sh = V.s;
+  return TDDE_OK;
+}
+
+tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
+  if (!c || !o) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (c->assembled) return fail(c, TDDE_ERR_STATE, "operator already assembled");
+  const int nr = c->d.nr, nang = c->d.nang, hb = c->d.half_band, nb = 2 * hb + 1;
+  if (!o->kappa) return fail(c, TDDE_ERR_ARG, "kappa is required");
+  if (o->n_h < 0 || o->n_h > 4 || (o->n_h > 0 && !o->h_poly)) return fail(c, TDDE_ERR_ARG, "n_h must be 0..4 with h_poly");
+  if (o->n_s < 0 || o->n_s > 3 || (o->n_s > 0 && !o->s_poly)) return fail(c, TDDE_ERR_ARG, "n_s must be 0..3 with s_poly");
+  if (o->n_terms < 0 || o->n_terms > kMaxTerms) return fail(c, TDDE_ERR_ARG, "n_terms must be 0..32");
+  if (o->n_terms > 0 && (!o->a_rowptr || !o->a_off || !o->a_col || !o->a_val || !o->r_band || !o->kpow || !o->coef ||
+                         !o->field))
+    return fail(c, TDDE_ERR_ARG, "coupling arrays missing");
+  // validate CSR and fold kappa exponents into the values
+  std::vector<int> rowptr_abs((size_t)o->n_terms * (nang + 1));
+  std::vector<double> tval;
+  std::vector<int> pq(o->n_terms);
+  const int64_t nnz = o->n_terms ? o->a_off[o->n_terms] : 0;
+  if (nnz > INT32_MAX) return fail(c, TDDE_ERR_ARG, "too many coupling nonzeros");
+  tval.resize(nnz);
+  for (int m = 0; m < o->n_terms; ++m) {
+    const int64_t off = o->a_off[m], off1 = o->a_off[m + 1];
+    const int32_t* rp = o->a_rowptr + (size_t)m * (nang + 1);
+    if (off < 0 || off1 < off || rp[0] != 0 || rp[nang] != off1 - off)
+      return fail(c, TDDE_ERR_ARG, "term " + std::to_string(m) + ": inconsistent row pointers / offsets");
+    if (o->field[m] < 0 || o->field[m] >= c->d.n_fields)
+      return fail(c, TDDE_ERR_ARG, "term " + std::to_string(m) + ": field index out of range");
+    const int ka = o->kpow[2 * m], kb = o->kpow[2 * m + 1];
+    if (ka < 0 || ka > 3 || kb < 0 || kb > 3) return fail(c, TDDE_ERR_ARG, "kappa exponents must be 0..3");
+    for (int j = 0; j <= nang; ++j) {
+      if (j < nang && rp[j + 1] < rp[j]) return fail(c, TDDE_ERR_ARG, "row pointers not monotone");
+      rowptr_abs[(size_t)m * (nang + 1) + j] = (int)(off + rp[j]);
+    }
+    for (int j = 0; j < nang; ++j)
+      for (int p = rp[j]; p < rp[j + 1]; ++p) {
+        const int jj = o->a_col[off + p];
+        if (jj < 0 || jj >= nang) return fail(c, TDDE_ERR_ARG, "column index out of range");
+        tval[off + p] = std::pow(o->kappa[j], ka) * o->a_val[off + p] * std::pow(o->kappa[jj], kb);
+      }
+    pq[m] = any_offdiag(o->r_band + (size_t)m * 4 * nb * nr, 1, hb, nr, 1) ? 1 : 0;
+  }
+  tdde_status s;
+  if ((s = build_devop<double>(c, o, c->op64, tval, rowptr_abs, pq)) != TDDE_OK) return s;
+  if ((s = build_devop<float>(c, o, c->op32, tval, rowptr_abs, pq)) != TDDE_OK) return s;
+  // host copies for the preconditioner
+  const size_t bsz = (size_t)4 * nb * nr;
+  c->kappa.assign(o->kappa, o->kappa + nang);
+  c->n_h = o->n_h;
+  c->n_s = o->n_s;
+  c->has_chan = o->h_chan != nullptr;
+  if (o->n_h) c->h_poly.assign(o->h_poly, o->h_poly + o->n_h * bsz);
+  if (o->n_s) c->s_poly.assign(o->s_poly, o->s_poly + o->n_s * bsz);
+  if (o->h_chan) c->h_chan.assign(o->h_chan, o->h_chan + (size_t)nang * bsz * 2);
+  // factor blocks: one per channel with its own complex band, else one per distinct kappa
+  c->block_of.assign(nang, 0);
+  if (c->has_chan) {
+    for (int j = 0; j < nang; ++j) c->block_of[j] = j;
+    c->nblk = nang;
+  } else {
+    std::map<double, int> seen;
+    for (int j = 0; j < nang; ++j) {
+      auto it = seen.find(o->kappa[j]);
+      if (it == seen.end()) it = seen.emplace(o->kappa[j], (int)seen.size()).first;
+      c->block_of[j] = it->second;
+    }
+    c->nblk = (int)seen.size();
+  }
+  // workspace
+  const size_t n = (size_t)c->d.batch * c->E;
+  if ((s = alloc_kvec<double>(c, c->v64, c->v64np, n)) != TDDE_OK) return s;
+  if ((s = alloc_kvec<float>(c, c->v32, c->v32np, n)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->bvec, n)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->r64, n)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->rhs32, n)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->fvals, (size_t)c->d.batch * c->d.n_fields)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->pulses, (size_t)c->d.batch * c->d.n_fields)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->n_steps_dev, (size_t)c->d.batch)) != TDDE_OK) return s;
+  // persistent grid: as many work-groups as can be co-resident
+  int dev = 0, ncu = 0, per_cu = 0;
+  HIP_TRY(c, hipGetDevice(&dev));
+  HIP_TRY(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(persistent_kernel),
+                                                          kThreads, 0));
+  if (per_cu <= 0) return fail(c, TDDE_ERR_HIP, "persistent kernel cannot be resident");
+  per_cu = std::min(per_cu, 4);
+  int n_wg = ncu * per_cu;
+  if (c->d.batch > n_wg) return fail(c, TDDE_ERR_ARG, "batch larger than the co-resident work-group count");
+  c->G = n_wg / c->d.batch;
+  // multiple of 8 work-groups per instance keeps a tile of every instance on one XCD
+  if (c->G >= 8) c->G -= c->G % 8;
+  c->n_wg = n_wg;
+  if ((s = dev_alloc(c, &c->part, (size_t)c->d.batch * c->G * kSlots)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->bar, 4)) != TDDE_OK) return s;
+  c->n_counters = 64 * kCounterPerStep;
+  if ((s = dev_alloc(c, &c->counters, (size_t)c->n_counters)) != TDDE_OK) return s;
+  c->stats_cap = c->d.batch;
+  if ((s = dev_alloc(c, &c->stats_dev, (size_t)c->stats_cap)) != TDDE_OK) return s;
+  HIP_TRY(c, hipDeviceSynchronize());
+  c->assembled = true;
+  return TDDE_OK;
+}
+
+tdde_status tdde_launch_info(tdde_ctx* c, int32_t* n_wg, int32_t* per_inst) {
+  if (!c || !n_wg || !per_inst) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  *n_wg = c->n_wg;
+  *per_inst = c->G;
+  return TDDE_OK;
+}
+
+// Banded LU of M = S + i dt/2 H0 for one block, rows q = 2 i + s, plus segment coupling matrices.
+static void factor_block(const tdde_ctx* c, int j, double dt, int m, int P, std::vector<cd>& LU, std::vector<cd>& TL,
+                         std::vector<cd>& TU) {
+  const int nr = c->d.nr, hb = c->d.half_band, n = 2 * nr, w = 2 * hb + 1, ws = 2 * w + 1;
+  const double kap = c->kappa[j];
+  std::vector<cd> A((size_t)n * ws, cd(0, 0));  // A[q][k + w] = M(q, q + k)
+  for (int s = 0; s < 2; ++s)
+    for (int s2 = 0; s2 < 2; ++s2)
+      for (int d = -hb; d <= hb; ++d)
+        for (int i = 0; i < nr; ++i) {
+          const int i2 = i + d;
+          if (i2 < 0 || i2 >= nr) continue;
+          const int bi = band_index(hb, nr, s, s2, d, i);
+          double sv = 0.0, hv = 0.0, hvi = 0.0, kn = 1.0;
+          for (int k = 0; k < c->n_s; ++k, kn *= kap) sv += kn * c->s_poly[(size_t)k * 4 * (2 * hb + 1) * nr + bi];
+          if (c->n_s == 0 && d == 0 && s == s2) sv = 1.0;
+          kn = 1.0;
+          for (int k = 0; k < c->n_h; ++k, kn *= kap) hv += kn * c->h_poly[(size_t)k * 4 * (2 * hb + 1) * nr + bi];
+          if (c->has_chan) {
+            const size_t ci = ((size_t)j * 4 * (2 * hb + 1) * nr + bi) * 2;
+            hv += c->h_chan[ci];
+            hvi += c->h_chan[ci + 1];
+          }
+          // M = S + i dt/2 (hv + i hvi)
+          const cd val = cd(sv, 0.0) + cd(0.0, 0.5 * dt) * cd(hv, hvi);
+          const int q = 2 * i + s, q2 = 2 * i2 + s2;
+          A[(size_t)q * ws + (q2 - q) + w] += val;
+        }
+  for (int q = 0; q < n; ++q) {
+    const cd piv = A[(size_t)q * ws + w];
+    for (int r = q + 1; r <= std::min(q + w, n - 1); ++r) {
+      cd& arq = A[(size_t)r * ws + (q - r) + w];
+      if (arq == cd(0, 0)) continue;
+      const cd l = arq / piv;
+      arq = l;
+      for (int cc = q + 1; cc <= std::min(q + w, n - 1); ++cc)
+        A[(size_t)r * ws + (cc - r) + w] -= l * A[(size_t)q * ws + (cc - q) + w];
+    }
+  }
+  auto Lq = [&](int q, int col) -> cd { return (col < 0 || q - col > w || col >= q) ? cd(0, 0) : A[(size_t)q * ws + (col - q) + w]; };
+  auto Uq = [&](int q, int col) -> cd { return (col >= n || col - q > w || col <= q) ? cd(0, 0) : A[(size_t)q * ws + (col - q) + w]; };
+  LU.assign((size_t)n * ws, cd(0, 0));
+  for (int q = 0; q < n; ++q) {
+    for (int k = 0; k < w; ++k) LU[(size_t)q * ws + k] = Lq(q, q - 1 - k);
+    LU[(size_t)q * ws + w] = cd(1.0, 0.0) / A[(size_t)q * ws + w];
+    for (int k = 0; k < w; ++k) LU[(size_t)q * ws + w + 1 + k] = Uq(q, q + 1 + k);
+  }
+  TL.assign((size_t)P * w * w, cd(0, 0));
+  TU.assign((size_t)P * w * w, cd(0, 0));
+  std::vector<cd> W;
+  for (int p = 0; p < P; ++p) {
+    const int o = p * m, len = std::min(m, n - o);
+    if (p >= 1) {  // lower: W = L_pp^-1 C_p, C_p[r][c] = L(o + r, o - w + c)
+      W.assign((size_t)len * w, cd(0, 0));
+      for (int r = 0; r < len; ++r)
+        for (int cc = 0; cc < w; ++cc) {
+          cd v = Lq(o + r, o - w + cc);
+          for (int k = 1; k <= w && r - k >= 0; ++k) v -= Lq(o + r, o + r - k) * W[(size_t)(r - k) * w + cc];
+          W[(size_t)r * w + cc] = v;
+        }
+      for (int rr = 0; rr < w; ++rr)
+        for (int cc = 0; cc < w; ++cc) TL[((size_t)p * w + rr) * w + cc] = W[(size_t)(len - w + rr) * w + cc];
+    }
+    if (p <= P - 2) {  // upper: W = U_pp^-1 D_p, D_p[r][c] = U(o + r, o + len + c)
+      W.assign((size_t)len * w, cd(0, 0));
+      const int o2 = o + len;
+      for (int r = len - 1; r >= 0; --r)
+        for (int cc = 0; cc < w; ++cc) {
+          cd v = Uq(o + r, o2 + cc);
+          for (int k = 1; k <= w && r + k < len; ++k) v -= Uq(o + r, o + r + k) * W[(size_t)(r + k) * w + cc];
+          W[(size_t)r * w + cc] = v * LU[(size_t)(o + r) * ws + w];
+        }
+      for (int rr = 0; rr < w; ++rr)
+        for (int cc = 0; cc < w; ++cc) TU[((size_t)p * w + rr) * w + cc] = W[(size_t)rr * w + cc];
+    }
+  }
+}
+
+tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
+  if (!c) return TDDE_ERR_ARG;
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, TDDE_ERR_ARG, "dt must be positive and finite");
+  c->dt = dt;
+  c->dt_set = true;
+  const int nr = c->d.nr, hb = c->d.half_band, n = 2 * nr, w = 2 * hb + 1, ws = 2 * w + 1;
+  if (w != kPrecW) return TDDE_OK;  // preconditioner available for half_band 6 only (checked at solve)
+  if (n < w) return TDDE_OK;
+  const int m = std::max(w, (n + kMaxSeg - 1) / kMaxSeg);
+  const int P = (n + m - 1) / m;
+  std::vector<cd> LU, TL, TU;
+  std::vector<cd> allLU((size_t)c->nblk * n * ws), allTL((size_t)c->nblk * P * w * w), allTU((size_t)c->nblk * P * w * w);
+  std::vector<int> rep(c->nblk, -1);
+  for (int j = 0; j < c->d.nang; ++j)
+    if (rep[c->block_of[j]] < 0) rep[c->block_of[j]] = j;
+  for (int bk = 0; bk < c->nblk; ++bk) {
+    factor_block(c, rep[bk], dt, m, P, LU, TL, TU);
+    std::copy(LU.begin(), LU.end(), allLU.begin() + (size_t)bk * n * ws);
+    std::copy(TL.begin(), TL.end(), allTL.begin() + (size_t)bk * P * w * w);
+    std::copy(TU.begin(), TU.end(), allTU.begin() + (size_t)bk * P * w * w);
+  }
+  tdde_status s;
+  if (!c->prec_alloc) {
+    if ((s = dev_alloc(c, (double2**)&c->pc64.LU, allLU.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (double2**)&c->pc64.TL, allTL.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (double2**)&c->pc64.TU, allTU.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (float2**)&c->pc32.LU, allLU.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (float2**)&c->pc32.TL, allTL.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (float2**)&c->pc32.TU, allTU.size())) != TDDE_OK) return s;
+    if ((s = upload(c, (int**)&c->pc64.block_of, c->block_of.data(), c->block_of.size())) != TDDE_OK) return s;
+    c->pc32.block_of = c->pc64.block_of;
+    c->prec_alloc = true;
+  }
+  c->pc64.n = c->pc32.n = n;
+  c->pc64.m = c->pc32.m = m;
+  c->pc64.P = c->pc32.P = P;
+  HIP_TRY(c, hipMemcpy((void*)c->pc64.LU, allLU.data(), allLU.size() * sizeof(cd), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy((void*)c->pc64.TL, allTL.data(), allTL.size() * sizeof(cd), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy((void*)c->pc64.TU, allTU.data(), allTU.size() * sizeof(cd), hipMemcpyHostToDevice));
+  auto tof = [](const std::vector<cd>& v) {
+    std::vector<float> f(2 * v.size());
+    for (size_t i = 0; i < v.size(); ++i) { f[2 * i] = (float)v[i].real(); f[2 * i + 1] = (float)v[i].imag(); }
+    return f;
+  };
+  std::vector<float> f;
+  f = tof(allLU);
+  HIP_TRY(c, hipMemcpy((void*)c->pc32.LU, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  f = tof(allTL);
+  HIP_TRY(c, hipMemcpy((void*)c->pc32.TL, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  f = tof(allTU);
+  HIP_TRY(c, hipMemcpy((void*)c->pc32.TU, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  return TDDE_OK;
+}
+
+tdde_status tdde_set_pulses(tdde_ctx* c, const tdde_pulse* p) {
+  if (!c || !p) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  const size_t n = (size_t)c->d.batch * c->d.n_fields;
+  std::vector<PulseDev> h(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (!(p[i].T > 0.0)) return fail(c, TDDE_ERR_ARG, "pulse duration must be positive");
+    h[i] = PulseDev{p[i].amp, p[i].T, p[i].omega, p[i].phase, p[i].envelope, 0};
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->pulses, h.data(), n * sizeof(PulseDev), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->pulses_set = true;
+  return TDDE_OK;
+}
+
+tdde_status tdde_set_field(tdde_ctx* c, const double* f) {
+  if (!c || !f) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  HIP_TRY(c, hipMemcpyAsync(c->fvals, f, (size_t)c->d.batch * c->d.n_fields * sizeof(double), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->field_set = true;
+  return TDDE_OK;
+}
+
+template <typename T>
+static tdde_status launch_apply(tdde_ctx* c, const DevOp<T>& op, tdde_c128 as, tdde_c128 ah, const void* x, void* y) {
+  if (!c || !x || !y) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled || !c->field_set) return fail(c, TDDE_ERR_STATE, "assemble and set_field first");
+  if (x == y) return fail(c, TDDE_ERR_ARG, "x and y must differ");
+  dim3 grid(op.n_itiles, c->d.nang, c->d.batch);
+  hipLaunchKernelGGL(apply_kernel<T>, grid, dim3(kThreads), 0, c->stream, op, (const c2_t<T>*)x, (c2_t<T>*)y,
+                     make_double2(as.re, as.im), make_double2(ah.re, ah.im), (const double*)c->fvals, c->d.n_fields,
+                     c->E);
+  HIP_TRY(c, hipGetLastError());
+  return TDDE_OK;
+}
+
+tdde_status tdde_apply(tdde_ctx* c, tdde_c128 as, tdde_c128 ah, const void* x, void* y) {
+  return c ? launch_apply<double>(c, c->op64, as, ah, x, y) : TDDE_ERR_ARG;
+}
+tdde_status tdde_apply_c64(tdde_ctx* c, tdde_c128 as, tdde_c128 ah, const void* x, void* y) {
+  return c ? launch_apply<float>(c, c->op32, as, ah, x, y) : TDDE_ERR_ARG;
+}
+
+tdde_status tdde_precond_apply(tdde_ctx* c, const void* v, void* z) {
+  if (!c || !v || !z) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->dt_set || !c->prec_alloc) return fail(c, TDDE_ERR_STATE, "set_dt first (half_band 6 only)");
+  if (v == z) return fail(c, TDDE_ERR_ARG, "input and output must differ");
+  hipLaunchKernelGGL(precond_kernel<double>, dim3(c->d.nang, c->d.batch), dim3(64), 0, c->stream, c->pc64, c->d.nr,
+                     (const double2*)v, (double2*)z, c->E);
+  HIP_TRY(c, hipGetLastError());
+  return TDDE_OK;
+}
+
+static tdde_status check_opts(tdde_ctx* c, const tdde_solve_opts* o) {
+  if (!o) return fail(c, TDDE_ERR_ARG, "null options");
+  if (!(o->tol > 0.0) || o->max_iter <= 0) return fail(c, TDDE_ERR_ARG, "tol > 0 and max_iter > 0 required");
+  if (o->guess < 0 || o->guess > 2) return fail(c, TDDE_ERR_ARG, "unknown guess mode");
+  if (o->precision != TDDE_PREC_FP64 && o->precision != TDDE_PREC_MIXED) return fail(c, TDDE_ERR_ARG, "precision");
+  if (o->precision == TDDE_PREC_MIXED && (!(o->inner_tol > 0.0) || o->max_outer <= 0 || o->max_outer > 60))
+    return fail(c, TDDE_ERR_ARG, "mixed precision needs inner_tol > 0 and 1 <= max_outer <= 60");
+  if (o->precond && !c->prec_alloc) return fail(c, TDDE_ERR_STATE, "preconditioner needs set_dt and half_band 6");
+  return TDDE_OK;
+}
+
+static tdde_status run_persistent(tdde_ctx* c, SolveArgs& a, int n_chunk) {
+  if (n_chunk > 64) return fail(c, TDDE_ERR_ARG, "at most 64 steps per launch");
+  hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->counters),
+                     c->n_counters);
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, c->stream, c->bar, 4);
+  HIP_TRY(c, hipGetLastError());
+  void* args[] = {&a};
+  HIP_TRY(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(persistent_kernel), dim3(c->n_wg),
+                                        dim3(kThreads), args, 0, c->stream));
+  return TDDE_OK;
+}
+
+static SolveArgs base_args(tdde_ctx* c, const tdde_solve_opts* o) {
+  SolveArgs a{};
+  a.op64 = c->op64;
+  a.op32 = c->op32;
+  a.pc64 = c->pc64;
+  a.pc32 = c->pc32;
+  a.use_prec = o->precond ? 1 : 0;
+  a.v64 = a.use_prec ? c->v64 : c->v64np;
+  a.v32 = a.use_prec ? c->v32 : c->v32np;
+  a.bvec = c->bvec;
+  a.r64 = c->r64;
+  a.rhs32 = c->rhs32;
+  a.B = c->d.batch;
+  a.G = c->G;
+  a.E = c->E;
+  a.n_wg = c->n_wg;
+  a.guess = o->guess;
+  a.mixed = o->precision == TDDE_PREC_MIXED;
+  a.max_iter = o->max_iter;
+  a.max_outer = o->max_outer;
+  a.tol = o->tol;
+  a.inner_tol = o->inner_tol;
+  a.dt = c->dt;
+  a.n_fields = c->d.n_fields;
+  a.pulses = c->pulses;
+  a.fvals = c->fvals;
+  a.part = c->part;
+  a.bar = c->bar;
+  a.counters = c->counters;
+  a.stats = c->stats_dev;
+  a.n_chunk = 1;
+  return a;
+}
+
+static tdde_status collect_stats(tdde_ctx* c, tdde_solve_stats* out) {
+  std::vector<StatsDev> h(c->d.batch);
+  HIP_TRY(c, hipMemcpyAsync(h.data(), c->stats_dev, h.size() * sizeof(StatsDev), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned barh[4] = {0, 0, 0, 0};
+  HIP_TRY(c, hipMemcpy(barh, c->bar, sizeof(barh), hipMemcpyDeviceToHost));
+  if (barh[2] != 0) return fail(c, TDDE_ERR_HIP, "grid barrier timed out (work-groups not co-resident)");
+  tdde_status worst = TDDE_OK;
+  for (int b = 0; b < c->d.batch; ++b) {
+    tdde_solve_stats& s = out[b];
+    s.status = h[b].status;
+    s.iters = h[b].iters;
+    s.matvecs = h[b].matvecs;
+    s.restarts = h[b].restarts;
+    s.outer_iters = h[b].outer_iters;
+    s.pad_ = 0;
+    s.rel_res = h[b].rel_res;
+    s.true_rel_res = h[b].true_rel_res;
+    if (h[b].status == 2) worst = TDDE_BREAKDOWN;
+    else if (h[b].status != 0 && worst == TDDE_OK) worst = TDDE_NOT_CONVERGED;
+  }
+  return worst;
+}
+
+tdde_status tdde_solve(tdde_ctx* c, const void* b, void* x, const tdde_solve_opts* o, tdde_solve_stats* stats) {
+  if (!c || !b || !x) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled || !c->dt_set || !c->field_set) return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_field first");
+  tdde_status s = check_opts(c, o);
+  if (s != TDDE_OK) return s;
+  if (o->guess == TDDE_GUESS_PREV) return fail(c, TDDE_ERR_ARG, "solve takes a ZERO or GIVEN guess");
+  SolveArgs a = base_args(c, o);
+  a.mode = MODE_SOLVE;
+  a.b_in = (const double2*)b;
+  a.x_io = (double2*)x;
+  if ((s = run_persistent(c, a, 1)) != TDDE_OK) return s;
+  if (!stats) return TDDE_OK;
+  return collect_stats(c, stats);
+}
+
+tdde_status tdde_step(tdde_ctx* c, void* psi, double t, const void* guess, const tdde_solve_opts* o,
+                      tdde_solve_stats* stats) {
+  if (!c || !psi) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled || !c->dt_set || !c->pulses_set) return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_pulses first");
+  tdde_status s = check_opts(c, o);
+  if (s != TDDE_OK) return s;
+  if (o->guess == TDDE_GUESS_GIVEN && !guess) return fail(c, TDDE_ERR_ARG, "GIVEN guess needs guess_dev");
+  SolveArgs a = base_args(c, o);
+  a.mode = MODE_STEP;
+  a.psi = (double2*)psi;
+  a.guess_in = (const double2*)guess;
+  a.t0 = t;
+  a.step0 = 0;
+  a.n_steps = nullptr;
+  if ((s = run_persistent(c, a, 1)) != TDDE_OK) return s;
+  if (!stats) return TDDE_OK;
+  return collect_stats(c, stats);
+}
+
+tdde_status tdde_run_batched(tdde_ctx* c, void* psi, double t0, int32_t step0, int32_t n_chunk, const int32_t* n_steps,
+                             const tdde_solve_opts* o, void* stats_dev) {
+  if (!c || !psi || !n_steps) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled || !c->dt_set || !c->pulses_set) return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_pulses first");
+  tdde_status s = check_opts(c, o);
+  if (s != TDDE_OK) return s;
+  if (o->guess == TDDE_GUESS_GIVEN) return fail(c, TDDE_ERR_ARG, "batched runs take ZERO or PREV guesses");
+  if (n_chunk <= 0 || n_chunk > 64 || step0 < 0) return fail(c, TDDE_ERR_ARG, "1 <= n_chunk <= 64, step0 >= 0");
+  HIP_TRY(c, hipMemcpyAsync(c->n_steps_dev, n_steps, (size_t)c->d.batch * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  SolveArgs a = base_args(c, o);
+  a.mode = MODE_STEP;
+  a.psi = (double2*)psi;
+  a.t0 = t0;
+  a.step0 = step0;
+  a.n_chunk = n_chunk;
+  a.n_steps = c->n_steps_dev;
+  a.stats = (StatsDev*)stats_dev;
+  return run_persistent(c, a, n_chunk);
+}
+
