@@ -1,0 +1,224 @@
+"""Benchmark of the Crank-Nicolson / BiCGSTAB time step on one MI355X.
+
+Default workload: the hydrogen dipole case (DKB B-splines, Nr = 2000 radial pairs on [0, 200],
+41 kappa channels at mu = 1/2, N = 164000 complex128 unknowns, dt = 2e-4, ground state start,
+sin^2 pulse with 8 cycles at omega = 0.057, E0 = 0.05), preconditioned FP64 BiCGSTAB to a relative
+residual of 1e-12. One "step" is one full time step of the hot path: field evaluation at the
+midpoint, right-hand side, initial guess, BiCGSTAB with the block LU preconditioner, true-residual
+check. Steps run in persistent launches of up to 64 steps; the timed region starts with the
+inputs resident in HBM.
+
+Prints one JSON line (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_iteration(E, op_bytes, prec_bytes, precond):
+    """Minimal HBM bytes of one BiCGSTAB iteration of the fused solver (see the design notes):
+    19 vector passes of E complex128 values, two operator applies (operator coefficients read once
+    each), and two preconditioner solves (factors read once each, input and output vectors counted
+    in the vector passes)."""
+    vec = 19 * E * 16
+    return vec + 2 * op_bytes + (2 * prec_bytes if precond else 0)
+
+
+def operator_bytes(op):
+    n = op.h_poly.size * 8 + op.s_poly.size * 8 + sum(t.r_band.size * 8 + t.a_val.size * 12 for t in op.terms)
+    if op.h_chan is not None:
+        n += op.h_chan.size * 16
+    return n
+
+
+def prec_factor_bytes(op):
+    nr, nblk = op.nr, (op.nang if op.h_chan is not None else len(set(op.kappa.tolist())))
+    n = 2 * nr
+    w = 2 * op.hb + 1
+    P = math.ceil(n / max(w, math.ceil(n / 64)))
+    return nblk * (n * (2 * w + 1) + 2 * P * w * w) * 16
+
+
+def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64):
+    """Run warmup + timed steps in persistent chunks; returns (ms_per_step, stats array, kernel_ms_list)."""
+    s = P.Solver(w.op, 1)
+    s.set_dt(w.dt)
+    s.set_pulses(w.pulses)
+    opts = P.solve_opts(tol=1e-12, max_iter=200, guess=guess, precond=precond)
+    psi = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    total = warmup + steps
+    n_steps = np.array([total], dtype=np.int32)
+    stats = torch.zeros(total * 40, dtype=torch.uint8, device="cuda:0")
+    # warmup
+    k = 0
+    while k < warmup:
+        n = min(chunk, warmup - k)
+        s.run_batched(psi, w.t0, k, n, n_steps, opts, stats[k * 40:(k + n) * 40])
+        k += n
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    while k < total:
+        n = min(chunk, total - k)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.run_batched(psi, w.t0, k, n, n_steps, opts, stats[k * 40:(k + n) * 40])
+        e1.record(stream)
+        evs.append((e0, e1, n))
+        k += n
+    end = torch.cuda.Event(enable_timing=True)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end)
+    launches = [(a.elapsed_time(b), n) for a, b, n in evs]
+    st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+    s.close()
+    return ms / steps, st[warmup:], launches, wall
+
+
+def spmv_measure(P, torch, w, reps=20):
+    """Standalone operator apply y = S x + i dt/2 H x: average kernel time (HIP events)."""
+    s = P.Solver(w.op, w.batch)
+    s.set_field(np.ones((w.batch, w.op.n_fields)) * 0.01)
+    x = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        s.apply(x, y, 1.0, 0.5j * w.dt)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        s.apply(x, y, 1.0, 0.5j * w.dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    s.close()
+    return ms
+
+
+def cpu_baseline(w, precond, budget_s=20.0):
+    """The oracle (CSR assembly once, preconditioned textbook BiCGSTAB per step) on the host cores."""
+    from oracle.assemble import Assembled
+    from oracle.step import BlockPreconditioner, cn_step
+    asm = Assembled(w.op)
+    M = BlockPreconditioner(asm, w.dt) if precond else None
+    psi = w.psi0[0]
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        psi, st = cn_step(asm, w.pulses[0], w.t0 + n * w.dt, w.dt, psi, guess="prev", precond=M)
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 50:
+            break
+    el = time.perf_counter() - t0
+    return n / el, n, el
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the beyond-dipole apply measurement")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2512_21697_amd as P
+    from workloads import dkb, synthetic
+
+    _log("bench: building hydrogen workload (Nr=2000, 41 channels)")
+    w = dkb.config2()
+    E = w.op.n_unknowns
+    _log(f"bench: gpu steps={args.steps} warmup={args.warmup}")
+    ms_step, st, launches, wall = run_gpu_steps(P, torch, w, args.steps, args.warmup, precond=1,
+                                                guess=P.GUESS_PREV)
+    iters = st["iters"].astype(float)
+    mv = st["matvecs"].astype(float)
+    ok = bool(np.all(st["status"] == 0))
+    # roofline of the persistent solver kernel (the only kernel of the timed region)
+    kern_ms = sum(t for t, _ in launches) / max(1, len(launches))
+    steps_per_launch = sum(n for _, n in launches) / max(1, len(launches))
+    opb, pcb = operator_bytes(w.op), prec_factor_bytes(w.op)
+    it_mean = float(iters.mean())
+    bytes_step = (2 + 2) * E * 16 + 2 * opb + it_mean * algorithmic_bytes_per_iteration(E, opb, pcb, True)
+    achieved = bytes_step * steps_per_launch / (kern_ms * 1e-3) / 1e9
+    res = {
+        "metric": "TDDE steps/s (hydrogen dipole, preconditioned FP64 BiCGSTAB to 1e-12)",
+        "value": 1000.0 / ms_step,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic (seeded generator; DKB hydrogen operator computed on the host)",
+        "config": {"workload": "hydrogen dipole: Nr=2000, Nang=41 (l<=20, mu=1/2), N=164000, dt=2e-4, "
+                               "E0=0.05, w=0.057, 8-cycle sin^2, ground-state start, tol 1e-12, "
+                               "block-LU preconditioner, previous-state guess",
+                   "batch": 1, "seq_len": None, "parallelism": "single GPU"},
+        "iters_per_step": it_mean,
+        "matvecs_per_step": float(mv.mean()),
+        "all_converged": ok,
+        "max_true_rel_res": float(st["true_rel_res"].max()),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "persistent_kernel", "kernel_ms_per_launch": kern_ms,
+                     "steps_per_launch": steps_per_launch, "alg_bytes_per_step": bytes_step},
+    }
+    if not args.no_extra:
+        _log("bench: beyond-dipole apply (Nr=4000, Nang=770, N=6.16e6)")
+        w3 = synthetic.config3()
+        ms3 = spmv_measure(P, torch, w3)
+        E3 = w3.op.n_unknowns
+        b3 = 2 * E3 * 16 + operator_bytes(w3.op)
+        res["spmv_beyond_dipole"] = {"ms": ms3, "alg_GBps": b3 / (ms3 * 1e-3) / 1e9,
+                                     "frac_hbm": b3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, "alg_bytes": b3,
+                                     "N": E3}
+        del w3
+    if not args.no_cpu:
+        _log("bench: cpu oracle baseline")
+        rate, n, el = cpu_baseline(w, True, args.cpu_budget)
+        res["cpu_baseline"] = {"value": rate, "unit": "steps/s", "cores": os.cpu_count(), "kind": "oracle",
+                               "sample": f"{n} steps of the same workload from the ground state "
+                                         f"({el:.1f} s; CSR assembly and LU factorisation excluded; "
+                                         f"scipy CSR matvec single-threaded)"}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -167,9 +167,12 @@ tdde_status tdde_step(tdde_ctx* ctx, void* psi_dev, double t, const void* guess_
 
 /* Advance every instance by up to n_chunk steps in one persistent launch. Instance b advances
  * from step index step0 while step < n_steps[b] (host array [batch]); time t = t0 + step * dt.
- * stats_dev: device array [n_chunk][batch] of tdde_solve_stats, or NULL. No host synchronisation. */
+ * guess_dev: device complex128 [batch][E] initial guess, required when opts->guess == GIVEN (then
+ * n_chunk must be 1), else ignored. stats_dev: device array [n_chunk][batch] of tdde_solve_stats,
+ * or NULL. No host synchronisation. */
 tdde_status tdde_run_batched(tdde_ctx* ctx, void* psi_dev, double t0, int32_t step0, int32_t n_chunk,
-                             const int32_t* n_steps, const tdde_solve_opts* opts, void* stats_dev);
+                             const int32_t* n_steps, const void* guess_dev, const tdde_solve_opts* opts,
+                             void* stats_dev);
 
 /* Release every device buffer of the context. Accepts NULL. */
 tdde_status tdde_destroy(tdde_ctx* ctx);

@@ -59,7 +59,10 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"),
 
 EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field", "tdde_apply",
            "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_step", "tdde_run_batched", "tdde_destroy",
-           "tdde_launch_info", "tdde_status_string", "tdde_last_error"]
+           "tdde_launch_info", "tdde_status_string", "tdde_last_error", "tdde_mlp_create", "tdde_mlp_destroy",
+           "tdde_mlp_param_count", "tdde_mlp_set_params", "tdde_mlp_get_params", "tdde_mlp_get_grads",
+           "tdde_mlp_forward", "tdde_mlp_backward", "tdde_mlp_adam", "tdde_mlp_set_pulses", "tdde_mlp_guess",
+           "tdde_mlp_last_error"]
 
 _lib = None
 
@@ -84,7 +87,7 @@ def load():
         "tdde_precond_apply": [P, P, P],
         "tdde_solve": [P, P, P, C.POINTER(SolveOpts), P],
         "tdde_step": [P, P, C.c_double, P, C.POINTER(SolveOpts), P],
-        "tdde_run_batched": [P, P, C.c_double, C.c_int32, C.c_int32, P, C.POINTER(SolveOpts), P],
+        "tdde_run_batched": [P, P, C.c_double, C.c_int32, C.c_int32, P, P, C.POINTER(SolveOpts), P],
         "tdde_destroy": [P],
         "tdde_launch_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
     }
@@ -96,6 +99,26 @@ def load():
     lib.tdde_status_string.restype = C.c_char_p
     lib.tdde_last_error.argtypes = [P]
     lib.tdde_last_error.restype = C.c_char_p
+    msig = {
+        "tdde_mlp_create": [C.c_int32, C.c_double, P, C.POINTER(P)],
+        "tdde_mlp_destroy": [P],
+        "tdde_mlp_set_params": [P, P],
+        "tdde_mlp_get_params": [P, P],
+        "tdde_mlp_get_grads": [P, P],
+        "tdde_mlp_forward": [P, P, C.c_int32, P],
+        "tdde_mlp_backward": [P, P, C.c_int32, C.POINTER(C.c_double)],
+        "tdde_mlp_adam": [P, C.c_float],
+        "tdde_mlp_set_pulses": [P, P, C.c_int32, C.c_int32],
+        "tdde_mlp_guess": [P, C.POINTER(P), C.c_int32, C.c_int64, C.c_int32, C.c_double, C.c_double, P],
+    }
+    for name, args in msig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.tdde_mlp_param_count.argtypes = []
+    lib.tdde_mlp_param_count.restype = C.c_int64
+    lib.tdde_mlp_last_error.argtypes = [P]
+    lib.tdde_mlp_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -263,7 +286,7 @@ class Solver:
                          allow=(TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN))
         return st, ([s.as_dict() for s in out] if stats else None)
 
-    def run_batched(self, psi, t0, step0, n_chunk, n_steps, opts, stats_dev=None):
+    def run_batched(self, psi, t0, step0, n_chunk, n_steps, opts, stats_dev=None, guess=None):
         ns = _np(n_steps, np.int32)
         if ns.shape != (self.batch,):
             raise ValueError("n_steps must have one entry per instance")
@@ -272,11 +295,104 @@ class Solver:
             if (stats_dev.dtype != torch.uint8 or not stats_dev.is_cuda or not stats_dev.is_contiguous()
                     or stats_dev.numel() < n_chunk * self.batch * STATS_DTYPE.itemsize):
                 raise ValueError("stats_dev must be a contiguous CUDA uint8 tensor of n_chunk*batch*40 bytes")
+        g = _buf(guess, self.batch * self.E) if guess is not None else None
         self._check(self.lib.tdde_run_batched(self.h, _buf(psi, self.batch * self.E), float(t0), int(step0),
-                                              int(n_chunk), ns.ctypes.data_as(C.c_void_p), C.byref(opts),
+                                              int(n_chunk), ns.ctypes.data_as(C.c_void_p), g, C.byref(opts),
                                               _ptr(stats_dev)))
 
     def launch_info(self):
         a, b = C.c_int32(), C.c_int32()
         self._check(self.lib.tdde_launch_info(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+
+class Net:
+    """The learned-guess network of include/tdde_mlp.h (parameters and training scratch on the GPU)."""
+
+    RAW = 16
+
+    def __init__(self, train_rows: int, tau: float, stream=None):
+        import torch
+        self.lib = load()
+        self.train_rows = int(train_rows)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.tdde_mlp_create(self.train_rows, float(tau), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != TDDE_OK:
+            raise TddeError(st, "tdde_mlp_create failed")
+        self.h = h
+        self.n_params = int(self.lib.tdde_mlp_param_count())
+        self.batch = None
+
+    def _check(self, st):
+        if st != TDDE_OK:
+            raise TddeError(st, self.lib.tdde_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tdde_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        a = _np(flat, np.float32)
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        self._check(self.lib.tdde_mlp_set_params(self.h, a.ctypes.data_as(C.c_void_p)))
+
+    def get_params(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.lib.tdde_mlp_get_params(self.h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def get_grads(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        self._check(self.lib.tdde_mlp_get_grads(self.h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def _raw(self, raw):
+        import torch
+        if raw.dtype != torch.float64 or not raw.is_cuda or raw.dim() != 2 or raw.shape[1] != self.RAW \
+                or not raw.is_contiguous() or not 0 < raw.shape[0] <= self.train_rows:
+            raise ValueError("raw samples must be a contiguous CUDA float64 [M][16] tensor, M <= train_rows")
+        return C.c_void_p(raw.data_ptr()), int(raw.shape[0])
+
+    def forward(self, raw, out):
+        import torch
+        p, M = self._raw(raw)
+        if out.dtype != torch.float32 or not out.is_cuda or out.numel() != 2 * M or not out.is_contiguous():
+            raise ValueError("out must be a contiguous CUDA float32 tensor of 2*M values")
+        self._check(self.lib.tdde_mlp_forward(self.h, p, M, C.c_void_p(out.data_ptr())))
+
+    def backward(self, raw):
+        p, M = self._raw(raw)
+        loss = C.c_double()
+        self._check(self.lib.tdde_mlp_backward(self.h, p, M, C.byref(loss)))
+        return loss.value
+
+    def adam(self, lr):
+        self._check(self.lib.tdde_mlp_adam(self.h, float(lr)))
+
+    def set_pulses(self, pulses):
+        batch, nf = len(pulses), len(pulses[0])
+        arr = (PulseC * (batch * nf))()
+        for b in range(batch):
+            for m in range(nf):
+                q = pulses[b][m]
+                arr[b * nf + m] = PulseC(q.amp, q.T, q.omega, q.phase, 1 if q.envelope else 0, 0)
+        self._check(self.lib.tdde_mlp_set_pulses(self.h, C.cast(arr, C.c_void_p), batch, nf))
+        self.batch = batch
+
+    def guess(self, hist, E, nr, t_n, dt, out):
+        """hist: 4 device complex128 tensors (psi_n .. psi_{n-3}), each [batch * E]."""
+        n = self.batch * E
+        ptrs = (C.c_void_p * 4)(*[_buf(h, n).value for h in hist])
+        self._check(self.lib.tdde_mlp_guess(self.h, ptrs, self.batch, int(E), int(nr), float(t_n), float(dt),
+                                            _buf(out, n)))

@@ -670,12 +670,13 @@ tdde_status tdde_step(tdde_ctx* c, void* psi, double t, const void* guess, const
 }
 
 tdde_status tdde_run_batched(tdde_ctx* c, void* psi, double t0, int32_t step0, int32_t n_chunk, const int32_t* n_steps,
-                             const tdde_solve_opts* o, void* stats_dev) {
+                             const void* guess, const tdde_solve_opts* o, void* stats_dev) {
   if (!c || !psi || !n_steps) return fail(c, TDDE_ERR_ARG, "null argument");
   if (!c->assembled || !c->dt_set || !c->pulses_set) return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_pulses first");
   tdde_status s = check_opts(c, o);
   if (s != TDDE_OK) return s;
-  if (o->guess == TDDE_GUESS_GIVEN) return fail(c, TDDE_ERR_ARG, "batched runs take ZERO or PREV guesses");
+  if (o->guess == TDDE_GUESS_GIVEN && (!guess || n_chunk != 1))
+    return fail(c, TDDE_ERR_ARG, "a GIVEN guess needs guess_dev and n_chunk == 1");
   if (n_chunk <= 0 || n_chunk > 64 || step0 < 0) return fail(c, TDDE_ERR_ARG, "1 <= n_chunk <= 64, step0 >= 0");
   HIP_TRY(c, hipMemcpyAsync(c->n_steps_dev, n_steps, (size_t)c->d.batch * sizeof(int), hipMemcpyHostToDevice, c->stream));
   SolveArgs a = base_args(c, o);
@@ -685,6 +686,7 @@ tdde_status tdde_run_batched(tdde_ctx* c, void* psi, double t0, int32_t step0, i
   a.step0 = step0;
   a.n_chunk = n_chunk;
   a.n_steps = c->n_steps_dev;
+  a.guess_in = (const double2*)guess;
   a.stats = (StatsDev*)stats_dev;
   return run_persistent(c, a, n_chunk);
 }

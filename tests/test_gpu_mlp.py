@@ -1,0 +1,173 @@
+"""GPU checks of the learned-guess network against the FP64 oracle (marked gpu).
+
+Tolerances: the GPU computes with BF16 weights, BF16 features and BF16 hidden activations with FP32
+accumulation; the oracle uses the same BF16-rounded weights and features in FP64 with unrounded
+activations. Outputs agree to 2e-2 relative (L2 over rows) and gradients to 5e-2 relative per
+tensor (a few BF16 roundings of ~4e-3 each along the chain).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mlp as omlp  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return True
+
+
+def _raw(rng, M):
+    hist = rng.standard_normal((5, M)) + 1j * rng.standard_normal((5, M))
+    raw = np.zeros((M, 16))
+    for k in range(5):
+        raw[:, 2 * k] = hist[k].real
+        raw[:, 2 * k + 1] = hist[k].imag
+    raw[:, 10] = rng.standard_normal(M) * 0.3
+    raw[:, 11] = rng.standard_normal(M) * 0.3
+    raw[:, 12] = (rng.random(M) < 0.5).astype(float)
+    return raw, hist
+
+
+def _params(rng):
+    p = {k: rng.standard_normal(v) for k, v in omlp.param_shapes().items()}
+    p["W1"] *= 0.3
+    p["W2"] *= 1.0 / 16
+    p["W3"] *= 1.0 / 16
+    p["b1"] *= 0.1
+    p["b2"] *= 0.1
+    p["c"] *= 0.5
+    return p
+
+
+def _oracle(p, raw, tau):
+    pb = dict(p)
+    for k in ("W1", "W2", "W3"):
+        pb[k] = omlp.bf16_round(p[k])
+    hist = np.stack([raw[:, 2 * k] + 1j * raw[:, 2 * k + 1] for k in range(5)])
+    x, u, rho = omlp.features(hist[:4], raw[:, 10], raw[:, 11], raw[:, 12], tau)
+    x = omlp.bf16_round(x)
+    out, cache = omlp.forward(pb, x, u, raw[:, 12])
+    return pb, out, cache, hist[4] / rho
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_forward_and_backward_match_oracle(gpu):
+    import paper_2512_21697_amd as P
+    rng = np.random.default_rng(0)
+    M, tau = 1000, 1e-3
+    raw, _ = _raw(rng, M)
+    p = _params(rng)
+    net = P.Net(4096, tau)
+    net.set_params(omlp.flatten(p).astype(np.float32))
+    rt = torch.from_numpy(raw).to(DEV)
+    out = torch.zeros(2 * M, dtype=torch.float32, device=DEV)
+    net.forward(rt, out)
+    torch.cuda.synchronize()
+    og = out.cpu().numpy().reshape(M, 2)
+    pb, oo, cache, tgt = _oracle(p, raw, tau)
+    ref = np.stack([oo.real, oo.imag], 1)
+    assert _rel(og, ref) < 2e-2
+    loss = net.backward(rt)
+    L, g = omlp.loss_and_grads(pb, oo, tgt, cache)
+    assert abs(loss - L) / L < 2e-2
+    gg = omlp.unflatten(net.get_grads().astype(np.float64))
+    for k in omlp.PARAM_ORDER:
+        assert _rel(gg[k], g[k]) < 5e-2, k
+
+
+def test_adam_step_matches_oracle(gpu):
+    import paper_2512_21697_amd as P
+    rng = np.random.default_rng(1)
+    M, tau = 512, 1e-3
+    raw, _ = _raw(rng, M)
+    p = _params(rng)
+    net = P.Net(1024, tau)
+    net.set_params(omlp.flatten(p).astype(np.float32))
+    net.backward(torch.from_numpy(raw).to(DEV))
+    g = net.get_grads().astype(np.float64)
+    net.adam(1e-3)
+    got = net.get_params().astype(np.float64)
+    pf = {"all": omlp.flatten(p).astype(np.float32).astype(np.float64)}
+    mm, vv = {"all": np.zeros_like(g)}, {"all": np.zeros_like(g)}
+    omlp.adam_update(pf, {"all": g}, mm, vv, 1, 1e-3)
+    assert np.max(np.abs(got - pf["all"])) < 1e-6
+
+
+def test_guess_kernel_matches_training_forward(gpu):
+    """The fused inference path (features built from state history) equals rho * forward(raw)."""
+    import paper_2512_21697_amd as P
+    from workloads.desc import Pulse
+    rng = np.random.default_rng(2)
+    B, nr, nang = 2, 40, 3
+    E = nang * 2 * nr
+    tau = 1e-3
+    p = _params(rng)
+    net = P.Net(B * E, tau)
+    net.set_params(omlp.flatten(p).astype(np.float32))
+    pulses = [[Pulse(0.4, 50.0, 0.9, 0.2, True)], [Pulse(0.2, 30.0, 1.3, 1.0, True)]]
+    net.set_pulses(pulses)
+    hist = [rng.standard_normal(B * E) + 1j * rng.standard_normal(B * E) for _ in range(4)]
+    hd = [torch.from_numpy(h).to(DEV) for h in hist]
+    out = torch.zeros(B * E, dtype=torch.complex128, device=DEV)
+    t_n, dt = 5.0, 0.01
+    net.guess(hd, E, nr, t_n, dt, out)
+    torch.cuda.synchronize()
+    raw = np.zeros((B * E, 16))
+    for k in range(4):
+        raw[:, 2 * k] = hist[k].real
+        raw[:, 2 * k + 1] = hist[k].imag
+    import math
+    for b in range(B):
+        q = pulses[b][0]
+        f = lambda t: q.amp * math.sin(math.pi * t / q.T) ** 2 * math.sin(q.omega * t + q.phase)
+        raw[b * E:(b + 1) * E, 10] = f(t_n + dt / 2)
+        raw[b * E:(b + 1) * E, 11] = f(t_n - dt / 2)
+    raw[:, 12] = ((np.arange(B * E) % E) // nr) % 2
+    fo = torch.zeros(2 * B * E, dtype=torch.float32, device=DEV)
+    net.forward(torch.from_numpy(raw).to(DEV), fo)
+    torch.cuda.synchronize()
+    fo = fo.cpu().numpy().reshape(-1, 2)
+    rho = np.sqrt(np.abs(hist[0]) ** 2 + np.abs(hist[1]) ** 2 + tau * tau)
+    ref = rho * (fo[:, 0] + 1j * fo[:, 1])
+    assert _rel(out.cpu().numpy(), ref) < 1e-5
+
+
+def test_learned_guess_reduces_iterations(gpu):
+    """Small batched problem: train on solver trajectories of 8 pulses, evaluate on 4 held-out pulses.
+    The network must not change the result (tolerance unchanged) and must save iterations over the
+    zero guess."""
+    import paper_2512_21697_amd as P
+    from paper_2512_21697_amd import learned
+    from workloads import synthetic
+    op, psi0, _ = synthetic.block_banded_operator(160, 6, 0)
+    train_p, train_n = synthetic.batched_pulses(range(1, 9))
+    train_n = np.minimum(train_n, 400)
+    raw = learned.collect_samples(torch, op, train_p, train_n, np.repeat(psi0[None], 8, 0), 1e-3, every=10,
+                                  rows_per_instance=512)
+    net = P.Net(8192, 1e-6)
+    net.set_params(learned.init_params(0, net.n_params))
+    losses = learned.train(torch, net, raw, n_iter=600, batch_rows=4096, lr=2e-3)
+    assert losses[-50:].mean() < 0.2 * losses[:10].mean()
+    ev_p, ev_n = synthetic.batched_pulses(range(20001, 20005))
+    ev_n = np.minimum(ev_n, 300)
+    psi_b = np.repeat(psi0[None], 4, 0)
+    res = {}
+    for mode in ("zero", "prev", "mlp"):
+        fin, st, el = learned.propagate(torch, op, ev_p, ev_n, psi_b, 1e-3, mode, net=net)
+        act = learned.active_mask(ev_n, st.shape[0])
+        assert np.all(st["status"][act] == 0)
+        res[mode] = (fin.cpu().numpy(), float(st["iters"][act].mean()))
+    for mode in ("prev", "mlp"):
+        d = np.linalg.norm(res[mode][0] - res["zero"][0]) / np.linalg.norm(res["zero"][0])
+        assert d < 1e-8, (mode, d)
+    assert res["mlp"][1] < res["zero"][1], res
