@@ -5,10 +5,10 @@
 // with H0_j = sum_n kappa_j^n h_n (+ per-channel complex band), S_j = sum_n kappa_j^n s_n or I.
 //
 // Work-group layout: 256 threads = 2 components x 128 radial points; thread (s, ii) owns
-// y[j][s][i0 + ii]. The x tile of channel j (with a halo of hb points) is staged in LDS; for
-// each coupling term the angular combination w = sum_j' A[j][j'] x[j'] is staged in LDS once
-// per tile, so the radial band contraction reads LDS and the angular gather is not repeated
-// per radial tap.
+// y[j][s][i0 + ii]. The x tile of channel j (with a halo of hb points) is staged in LDS; the
+// angular combinations w_m = sum_j' A_m[j][j'] x[j'] of all terms sharing one sparsity pattern are
+// staged in LDS together (each neighbouring x value is read once per pattern), so the radial band
+// contraction reads LDS and the angular gather is not repeated per radial tap or per term.
 #pragma once
 #include "common.hpp"
 
@@ -16,7 +16,7 @@ namespace tdde {
 
 template <typename T> struct TileLds {
   c2_t<T> xs[2][kHalo];
-  c2_t<T> ws[2][kHalo];
+  c2_t<T> ws[kMaxGroup][2][kHalo];
 };
 
 // Stage v[s'][i0-hb .. i0+kTileR+hb) of one channel into dst (zero outside [0, nr)).
@@ -31,19 +31,30 @@ __device__ inline void stage_channel(c2_t<T> (*dst)[kHalo], const c2_t<T>* __res
   }
 }
 
-// Stage w[s'][.] = sum_p val[p] * x[col[p]][s'][.] for the CSR row [p0, p1).
+// Stage w_k[s'][.] = sum_p val[p * K + k] * x[col[p]][s'][.] for the K terms of one pattern group and
+// the CSR row [p0, p1): every neighbouring x value is loaded once for all K terms.
 template <typename T>
-__device__ inline void stage_gather(c2_t<T> (*dst)[kHalo], const c2_t<T>* __restrict__ xinst, const int* __restrict__ col,
-                                    const T* __restrict__ val, int p0, int p1, int i0, int nr, int hb) {
+__device__ inline void stage_gather(c2_t<T> (*dst)[2][kHalo], const c2_t<T>* __restrict__ xinst, const int* __restrict__ col,
+                                    const T* __restrict__ val, int p0, int p1, int K, int i0, int nr, int hb) {
   const int w = kTileR + 2 * hb;
   const size_t cstride = (size_t)2 * nr;
   for (int k = threadIdx.x; k < 2 * w; k += kThreads) {
     const int s = k / w, kk = k - s * w, gi = i0 - hb + kk;
-    c2_t<T> acc = cmk<T>(0, 0);
+    c2_t<T> acc[kMaxGroup];
+#pragma unroll
+    for (int q = 0; q < kMaxGroup; ++q) acc[q] = cmk<T>(0, 0);
     if (gi >= 0 && gi < nr) {
-      for (int p = p0; p < p1; ++p) acc = rfma<T>(val[p], xinst[(size_t)col[p] * cstride + (size_t)s * nr + gi], acc);
+      for (int p = p0; p < p1; ++p) {
+        const c2_t<T> xv = xinst[(size_t)col[p] * cstride + (size_t)s * nr + gi];
+        const T* v = val + (size_t)(p - p0) * K;
+#pragma unroll
+        for (int q = 0; q < kMaxGroup; ++q)
+          if (q < K) acc[q] = rfma<T>(v[q], xv, acc[q]);
+      }
     }
-    dst[s][kk] = acc;
+#pragma unroll
+    for (int q = 0; q < kMaxGroup; ++q)
+      if (q < K) dst[q][s][kk] = acc[q];
   }
 }
 
@@ -95,26 +106,37 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
     if (op.n_s == 0) out.sx = L.xs[s][ii + hb];
   }
 
-  // coupling terms: stage the angular combination, then the radial band contraction
-  for (int m = 0; m < op.n_terms; ++m) {
-    const int* rp = op.t_rowptr + (size_t)m * (op.nang + 1);
+  // coupling terms: stage the angular combinations of a pattern group, then the band contractions
+  for (int gidx = 0; gidx < op.n_groups; ++gidx) {
+    const int f0 = op.g_first[gidx], K = op.g_first[gidx + 1] - f0;
+    const int* rp = op.g_rowptr + (size_t)gidx * (op.nang + 1);
     const int p0 = rp[j], p1 = rp[j + 1];
-    const double2 cf = coef_f[m];
-    if (p0 == p1 || (cf.x == 0.0 && cf.y == 0.0)) continue;  // uniform over the work-group
+    bool any = false;
+    for (int q = 0; q < K; ++q) {
+      const double2 cf = coef_f[op.g_term[f0 + q]];
+      any = any || cf.x != 0.0 || cf.y != 0.0;
+    }
+    if (p0 == p1 || !any) continue;  // uniform over the work-group
     __syncthreads();
-    stage_gather<T>(L.ws, xinst, op.t_col, op.t_val, p0, p1, i0, nr, hb);
+    stage_gather<T>(L.ws, xinst, op.g_col, op.g_val + op.g_voff[gidx] + (size_t)(p0 - rp[0]) * K, p0, p1, K, i0, nr,
+                    hb);
     __syncthreads();
     if (live) {
       const size_t bstride = (size_t)nb * nr;
-      const T* R = op.t_r + (size_t)m * 4 * bstride;
-      const bool pq = op.t_pq[m] != 0;
-      c2_t<T> acc = cmk<T>(0, 0);
-      for (int s2 = 0; s2 < 2; ++s2) {
-        if (!pq && s2 != s) continue;
-        const T* Rb = R + (size_t)(s * 2 + s2) * bstride + i;
-        for (int d = -hb; d <= hb; ++d) acc = rfma<T>(Rb[(size_t)(d + hb) * nr], L.ws[s2][ii + hb + d], acc);
+      for (int q = 0; q < K; ++q) {
+        const int m = op.g_term[f0 + q];
+        const double2 cf = coef_f[m];
+        if (cf.x == 0.0 && cf.y == 0.0) continue;
+        const T* R = op.t_r + (size_t)m * 4 * bstride;
+        const bool pq = op.t_pq[m] != 0;
+        c2_t<T> acc = cmk<T>(0, 0);
+        for (int s2 = 0; s2 < 2; ++s2) {
+          if (!pq && s2 != s) continue;
+          const T* Rb = R + (size_t)(s * 2 + s2) * bstride + i;
+          for (int d = -hb; d <= hb; ++d) acc = rfma<T>(Rb[(size_t)(d + hb) * nr], L.ws[q][s2][ii + hb + d], acc);
+        }
+        out.hx = cfma<T>(cmk<T>((T)cf.x, (T)cf.y), acc, out.hx);
       }
-      out.hx = cfma<T>(cmk<T>((T)cf.x, (T)cf.y), acc, out.hx);
     }
   }
   return out;

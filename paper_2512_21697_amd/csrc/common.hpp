@@ -10,6 +10,7 @@ constexpr int kThreads = 256;    // work-group size of every kernel
 constexpr int kTileR = 128;      // radial points per tile (x 2 spinor components = 256 threads)
 constexpr int kMaxHB = 8;        // largest supported radial half-bandwidth
 constexpr int kMaxTerms = 32;    // largest number of coupling terms
+constexpr int kMaxGroup = 8;     // coupling terms staged together (same angular sparsity pattern)
 constexpr int kMaxFields = 16;   // largest number of time functions per instance
 constexpr int kHalo = kTileR + 2 * kMaxHB;
 
@@ -57,9 +58,18 @@ template <typename T> struct DevOp {
   const T* h_poly;             // [n_h][2][2][nb][nr]
   const c2_t<T>* h_chan;       // [nang][2][2][nb][nr]
   const T* s_poly;             // [n_s][2][2][nb][nr]
-  const int* t_rowptr;         // [n_terms][nang+1], absolute offsets into t_col / t_val
-  const int* t_col;
-  const T* t_val;              // kappa_j^a * A[j][j'] * kappa_j'^b
+  // Terms with one angular sparsity pattern form a group and are staged together:
+  // group g holds terms g_term[g_first[g] .. g_first[g+1]); its pattern is g_rowptr[g][nang+1]
+  // (absolute offsets into g_col); the value of term k of the group at pattern entry p is
+  // g_val[g_voff[g] + (p - g_rowptr[g][0]) * K + k], K = group size, with the kappa exponents
+  // folded in: kappa_j^a * A[j][j'] * kappa_j'^b.
+  int n_groups;
+  const int* g_first;          // [n_groups + 1]
+  const int* g_term;           // [n_terms]
+  const int* g_rowptr;         // [n_groups][nang+1]
+  const int* g_col;
+  const long* g_voff;          // [n_groups]
+  const T* g_val;
   const T* t_r;                // [n_terms][2][2][nb][nr]
   const int* t_pq;             // [n_terms]
   const int* t_field;          // [n_terms]

@@ -237,9 +237,48 @@ static tdde_status build_devop(tdde_ctx* c, const tdde_operator_desc* o, DevOp<T
   } else {
     op.h_chan = nullptr;
   }
-  if ((s = upload(c, (int**)&op.t_rowptr, rowptr_abs.data(), rowptr_abs.size())) != TDDE_OK) return s;
-  if ((s = upload(c, (int**)&op.t_col, o->a_col, (size_t)nnz)) != TDDE_OK) return s;
-  if ((s = up((T**)&op.t_val, tval.data(), (size_t)nnz)) != TDDE_OK) return s;
+  // group terms with identical angular sparsity patterns (staged together by the apply)
+  {
+    std::vector<int> g_first{0}, g_term, g_rowptr, g_col;
+    std::vector<long> g_voff;
+    std::vector<double> g_val;
+    std::vector<char> used(o->n_terms, 0);
+    auto same = [&](int m1, int m2) {
+      const int32_t* r1 = o->a_rowptr + (size_t)m1 * (nang + 1);
+      const int32_t* r2 = o->a_rowptr + (size_t)m2 * (nang + 1);
+      for (int j = 0; j <= nang; ++j)
+        if (r1[j] != r2[j]) return false;
+      const int32_t* c1 = o->a_col + o->a_off[m1];
+      const int32_t* c2 = o->a_col + o->a_off[m2];
+      for (int p = 0; p < r1[nang]; ++p)
+        if (c1[p] != c2[p]) return false;
+      return true;
+    };
+    for (int m = 0; m < o->n_terms; ++m) {
+      if (used[m]) continue;
+      std::vector<int> grp{m};
+      used[m] = 1;
+      for (int m2 = m + 1; m2 < o->n_terms && (int)grp.size() < kMaxGroup; ++m2)
+        if (!used[m2] && same(m, m2)) { grp.push_back(m2); used[m2] = 1; }
+      const int32_t* rp = o->a_rowptr + (size_t)m * (nang + 1);
+      const int base = (int)g_col.size();
+      for (int j = 0; j <= nang; ++j) g_rowptr.push_back(base + rp[j]);
+      g_voff.push_back((long)g_val.size());
+      for (int p = 0; p < rp[nang]; ++p) {
+        g_col.push_back(o->a_col[o->a_off[m] + p]);
+        for (int q : grp) g_val.push_back(tval[o->a_off[q] + p]);
+      }
+      for (int q : grp) g_term.push_back(q);
+      g_first.push_back((int)g_term.size());
+    }
+    op.n_groups = (int)g_first.size() - 1;
+    if ((s = upload(c, (int**)&op.g_first, g_first.data(), g_first.size())) != TDDE_OK) return s;
+    if ((s = upload(c, (int**)&op.g_term, g_term.data(), g_term.size())) != TDDE_OK) return s;
+    if ((s = upload(c, (int**)&op.g_rowptr, g_rowptr.data(), g_rowptr.size())) != TDDE_OK) return s;
+    if ((s = upload(c, (int**)&op.g_col, g_col.data(), g_col.size())) != TDDE_OK) return s;
+    if ((s = upload(c, (long**)&op.g_voff, g_voff.data(), g_voff.size())) != TDDE_OK) return s;
+    if ((s = up((T**)&op.g_val, g_val.data(), g_val.size())) != TDDE_OK) return s;
+  }
   if ((s = up((T**)&op.t_r, o->n_terms ? o->r_band : nullptr, (size_t)o->n_terms * bsz)) != TDDE_OK) return s;
   if ((s = upload(c, (int**)&op.t_pq, pq.data(), pq.size())) != TDDE_OK) return s;
   if ((s = upload(c, (int**)&op.t_field, o->field, (size_t)o->n_terms)) != TDDE_OK) return s;
