@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the beyond-dipole apply measurement")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB once (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -217,6 +219,14 @@ def main():
                                "sample": f"{n} steps of the same workload from the ground state "
                                          f"({el:.1f} s; CSR assembly and LU factorisation excluded; "
                                          f"scipy CSR matvec single-threaded)"}
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 16
+        a = torch.ones(n, dtype=torch.complex128, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["copy_probe_bytes"] = 2 * n * 16
     print(json.dumps(res))
 
 
