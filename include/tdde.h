@@ -180,6 +180,12 @@ tdde_status tdde_destroy(tdde_ctx* ctx);
 /* Persistent-grid size actually used (work-groups) and the per-instance work-group count. */
 tdde_status tdde_launch_info(tdde_ctx* ctx, int32_t* n_wg, int32_t* wg_per_instance);
 
+/* Diagnostics: record up to cap phase timestamps of work-group 0 in every later persistent launch
+ * (value = (wall_clock64 << 8) | phase id; the device wall clock runs at 100 MHz on gfx950).
+ * cap = 0 disables. tdde_debug_read_marks synchronises the stream and copies them to the host. */
+tdde_status tdde_debug_phase_marks(tdde_ctx* ctx, int32_t cap);
+tdde_status tdde_debug_read_marks(tdde_ctx* ctx, uint64_t* host, int32_t cap);
+
 const char* tdde_status_string(tdde_status s);
 const char* tdde_last_error(const tdde_ctx* ctx); /* NULL ctx: last create error */
 

@@ -8,11 +8,14 @@
  *   rho   = sqrt(|psi_n|^2 + |psi_{n-1}|^2 + tau^2),   u_k = psi_{n-k} / rho   (k = 0..3)
  *   x     = [Re u_0, Im u_0, .., Re u_3, Im u_3, f(t_n + dt/2), f(t_n - dt/2), s, 0 x 21]  (32)
  *   h1    = silu(W1 x + b1), h2 = silu(W2 h1 + b2), y = W3 h2 + b3        (hidden width H = 256)
- *   guess = sum_k c[s][k] psi_{n-k} + rho (y_0 + i y_1)                    (linear skip per component)
+ *   out   = sum_k c[s][k] u_k + sigma (y_0 + i y_1),   guess = rho * out
  *
- * Weights are used in BF16 with FP32 accumulation (gfx950 MFMA 16x16x32 bf16); FP32 master
- * weights are updated by Adam. Flat FP32 parameter layout (tdde_mlp_param_count() values):
- *   W1[256][32], b1[256], W2[256][256], b2[256], W3[2][256], b3[2], c[2][4][2] (re, im)
+ * The linear skip c[s][k] (complex, FP64) is the least-squares four-step predictor of psi_{n+1}
+ * per spinor component s, fitted on the training rows (tdde_mlp_fit_skip); its coefficients are
+ * large and cancel, so it is kept and applied in FP64. sigma is the RMS residual of that fit, so
+ * the network learns the remainder at unit scale. Weights are used in BF16 with FP32 accumulation
+ * (gfx950 MFMA 16x16x32 bf16); FP32 master weights are updated by Adam. Flat FP32 parameter layout
+ * (tdde_mlp_param_count() values): W1[256][32], b1[256], W2[256][256], b2[256], W3[2][256], b3[2].
  *
  * Training rows ("raw samples", device float64 [M][16]) hold, per row:
  *   [0..9]  Re/Im of psi_n, psi_{n-1}, psi_{n-2}, psi_{n-3}, psi_{n+1}
@@ -45,12 +48,24 @@ tdde_status tdde_mlp_get_params(tdde_mlp* m, float* host);
 /* Last gradient (FP32, flat layout) to the host. */
 tdde_status tdde_mlp_get_grads(tdde_mlp* m, float* host);
 
+/* Least-squares fit of the skip coefficients on M raw samples (device float64 [M][16]): the Gram
+ * matrices sum conj(u_k) u_l and right-hand sides sum conj(u_k) psi_{n+1}/rho per component are
+ * reduced on the device in a fixed order, each 4x4 Hermitian system is solved on the device in
+ * FP64 (Gaussian elimination, partial pivoting), and sigma is set to the RMS residual of the fit
+ * (at least 1e-300). */
+tdde_status tdde_mlp_fit_skip(tdde_mlp* m, const double* raw, int32_t M);
+/* Set / read the skip coefficients c[2][4][2] (re, im) and sigma (host). */
+tdde_status tdde_mlp_set_skip(tdde_mlp* m, const double* c, double sigma);
+tdde_status tdde_mlp_get_skip(tdde_mlp* m, double* c, double* sigma);
+
 /* Forward pass on M raw samples (device float64 [M][16]); writes out[M][2] (device float32): the
- * network prediction of psi_{n+1} / rho (skip included). M <= train_rows. */
+ * residual of the prediction in units of sigma, (out - psi_{n+1}/rho) / sigma, formed in FP64
+ * (the residual is far below FP32 resolution of the prediction itself). M <= train_rows. */
 tdde_status tdde_mlp_forward(tdde_mlp* m, const double* raw, int32_t M, float* out);
 
-/* Forward + loss + backward on M raw samples: loss (host) = mean |out - psi_{n+1}/rho|^2;
- * gradients stay on the device (tdde_mlp_get_grads). */
+/* Forward + loss + backward on M raw samples: loss (host) = mean over rows of the squared residual
+ * |out - psi_{n+1}/rho|^2 / sigma^2; gradients of the FP32 parameters stay on the device
+ * (tdde_mlp_get_grads); the skip is not trained by gradients. */
 tdde_status tdde_mlp_backward(tdde_mlp* m, const double* raw, int32_t M, double* loss);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradients, then refresh the BF16

@@ -7,12 +7,12 @@ entry is one row) from the last four states and the field:
   u_k   = psi_{n-k} / rho,  k = 0..3                               (complex)
   x     = [Re u_0, Im u_0, ..., Re u_3, Im u_3, f(t_n + dt/2), f(t_n - dt/2), s, 0 ...]  (32 features)
   h1    = silu(W1 x + b1),  h2 = silu(W2 h1 + b2),  y = W3 h2 + b3   (256, 256, 2)
-  out   = sum_k c[s][k] u_k + (y_0 + i y_1)                          (learned linear skip per component)
-  guess = rho * out
+  out   = sum_k c[s][k] u_k + sigma (y_0 + i y_1),   guess = rho * out
 
-Loss: mean over rows of |out - psi_{n+1} / rho|^2. Adam (Kingma & Ba 2015) on all parameters.
-Parameters are a dict of float64 arrays: W1 [H][F], b1 [H], W2 [H][H], b2 [H], W3 [2][H], b3 [2],
-c [2][4][2] (re, im).
+c[s][k] is the least-squares four-step predictor of psi_{n+1} / rho per spinor component
+(``fit_skip``); sigma is the RMS residual of that fit. Loss: mean over rows of
+|out - psi_{n+1}/rho|^2 / sigma^2. Adam (Kingma & Ba 2015) on the network parameters, a dict of
+float64 arrays: W1 [H][F], b1 [H], W2 [H][H], b2 [H], W3 [2][H], b3 [2].
 """
 from __future__ import annotations
 
@@ -46,26 +46,40 @@ def features(hist, f_half, f_mhalf, s_flag, tau):
     return x, u, rho
 
 
-def forward(p, x, u, s_flag):
+def fit_skip(u, t, s_flag):
+    """Least-squares c[s] (complex [2][4]) with t ~ sum_k c[s][k] u_k per component; returns (c, sigma)."""
+    s = s_flag.astype(int)
+    c = np.zeros((2, 4), dtype=complex)
+    res2 = 0.0
+    for sv in (0, 1):
+        m = s == sv
+        X = u[:, m].T
+        c[sv], *_ = np.linalg.lstsq(X, t[m], rcond=None)
+        res2 += float(np.sum(np.abs(X @ c[sv] - t[m]) ** 2))
+    return c, max(np.sqrt(res2 / len(t)), 1e-300)
+
+
+def forward(p, x, u, s_flag, c, sigma):
+    """Prediction out = sum_k c[s][k] u_k + sigma (y_0 + i y_1) for every row."""
     z1 = x @ p["W1"].T + p["b1"]
     h1 = silu(z1)
     z2 = h1 @ p["W2"].T + p["b2"]
     h2 = silu(z2)
     y = h2 @ p["W3"].T + p["b3"]
-    c = p["c"][..., 0] + 1j * p["c"][..., 1]  # [2][4]
     s = s_flag.astype(int)
     lin = np.sum(c[s].T * u, axis=0)  # [M]
-    out = lin + (y[:, 0] + 1j * y[:, 1])
-    cache = dict(x=x, z1=z1, h1=h1, z2=z2, h2=h2, u=u, s=s)
+    out = lin + sigma * (y[:, 0] + 1j * y[:, 1])
+    cache = dict(x=x, z1=z1, h1=h1, z2=z2, h2=h2, u=u, s=s, sigma=sigma)
     return out, cache
 
 
 def loss_and_grads(p, out, target, cache):
-    """L = mean |out - target|^2; returns (L, grads dict) by the chain rule."""
+    """L = mean |out - target|^2 / sigma^2; returns (L, grads dict) by the chain rule."""
     M = out.shape[0]
-    e = out - target
+    sig = cache["sigma"]
+    e = (out - target) / sig
     L = float(np.mean(np.abs(e) ** 2))
-    dout = 2.0 * e / M  # dL/d(Re out) + i dL/d(Im out)
+    dout = 2.0 * e / M  # dL/dy_0 + i dL/dy_1 (y enters out as sigma * y)
     g = {}
     dy = np.stack([dout.real, dout.imag], axis=1)
     g["W3"] = dy.T @ cache["h2"]
@@ -78,15 +92,6 @@ def loss_and_grads(p, out, target, cache):
     dz1 = dh1 * dsilu(cache["z1"])
     g["W1"] = dz1.T @ cache["x"]
     g["b1"] = dz1.sum(0)
-    # out = sum_k c_k u_k: dL/dRe c = Re(conj(dout) u), dL/dIm c = Re(conj(dout) i u)
-    gc = np.zeros((2, 4, 2))
-    u, s = cache["u"], cache["s"]
-    for sv in (0, 1):
-        m = s == sv
-        for k in range(4):
-            gc[sv, k, 0] = np.sum((np.conj(dout[m]) * u[k, m]).real)
-            gc[sv, k, 1] = np.sum((np.conj(dout[m]) * 1j * u[k, m]).real)
-    g["c"] = gc
     return L, g
 
 
@@ -100,12 +105,12 @@ def adam_update(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
 
 
-PARAM_ORDER = ["W1", "b1", "W2", "b2", "W3", "b3", "c"]
+PARAM_ORDER = ["W1", "b1", "W2", "b2", "W3", "b3"]
 
 
 def param_shapes(hidden=256, n_feat=N_FEAT):
     return {"W1": (hidden, n_feat), "b1": (hidden,), "W2": (hidden, hidden), "b2": (hidden,), "W3": (2, hidden),
-            "b3": (2,), "c": (2, 4, 2)}
+            "b3": (2,)}
 
 
 def unflatten(flat, hidden=256):

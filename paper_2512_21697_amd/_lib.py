@@ -59,10 +59,11 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"),
 
 EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field", "tdde_apply",
            "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_step", "tdde_run_batched", "tdde_destroy",
-           "tdde_launch_info", "tdde_status_string", "tdde_last_error", "tdde_mlp_create", "tdde_mlp_destroy",
+           "tdde_launch_info", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
+           "tdde_debug_read_marks", "tdde_mlp_create", "tdde_mlp_destroy",
            "tdde_mlp_param_count", "tdde_mlp_set_params", "tdde_mlp_get_params", "tdde_mlp_get_grads",
            "tdde_mlp_forward", "tdde_mlp_backward", "tdde_mlp_adam", "tdde_mlp_set_pulses", "tdde_mlp_guess",
-           "tdde_mlp_last_error"]
+           "tdde_mlp_last_error", "tdde_mlp_fit_skip", "tdde_mlp_set_skip", "tdde_mlp_get_skip"]
 
 _lib = None
 
@@ -90,6 +91,8 @@ def load():
         "tdde_run_batched": [P, P, C.c_double, C.c_int32, C.c_int32, P, P, C.POINTER(SolveOpts), P],
         "tdde_destroy": [P],
         "tdde_launch_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+        "tdde_debug_phase_marks": [P, C.c_int32],
+        "tdde_debug_read_marks": [P, P, C.c_int32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -108,6 +111,9 @@ def load():
         "tdde_mlp_forward": [P, P, C.c_int32, P],
         "tdde_mlp_backward": [P, P, C.c_int32, C.POINTER(C.c_double)],
         "tdde_mlp_adam": [P, C.c_float],
+        "tdde_mlp_fit_skip": [P, P, C.c_int32],
+        "tdde_mlp_set_skip": [P, P, C.c_double],
+        "tdde_mlp_get_skip": [P, P, C.POINTER(C.c_double)],
         "tdde_mlp_set_pulses": [P, P, C.c_int32, C.c_int32],
         "tdde_mlp_guess": [P, C.POINTER(P), C.c_int32, C.c_int64, C.c_int32, C.c_double, C.c_double, P],
     }
@@ -300,6 +306,18 @@ class Solver:
                                               int(n_chunk), ns.ctypes.data_as(C.c_void_p), g, C.byref(opts),
                                               _ptr(stats_dev)))
 
+    def enable_marks(self, cap):
+        self._check(self.lib.tdde_debug_phase_marks(self.h, int(cap)))
+        self._marks_cap = int(cap)
+
+    def read_marks(self):
+        """Phase timestamps of work-group 0: list of (microseconds since the first mark, phase id)."""
+        a = np.zeros(self._marks_cap, dtype=np.uint64)
+        self._check(self.lib.tdde_debug_read_marks(self.h, a.ctypes.data_as(C.c_void_p), self._marks_cap))
+        a = a[a != 0]
+        t = (a >> np.uint64(8)).astype(np.float64) / 100.0  # 100 MHz wall clock -> microseconds
+        return list(zip((t - t[0]).tolist(), (a & np.uint64(0xFF)).astype(int).tolist())) if len(a) else []
+
     def launch_info(self):
         a, b = C.c_int32(), C.c_int32()
         self._check(self.lib.tdde_launch_info(self.h, C.byref(a), C.byref(b)))
@@ -379,6 +397,28 @@ class Net:
 
     def adam(self, lr):
         self._check(self.lib.tdde_mlp_adam(self.h, float(lr)))
+
+    def fit_skip(self, raw):
+        """Least-squares four-step skip on the device (any number of rows)."""
+        import torch
+        if raw.dtype != torch.float64 or not raw.is_cuda or raw.dim() != 2 or raw.shape[1] != self.RAW \
+                or not raw.is_contiguous() or raw.shape[0] <= 0:
+            raise ValueError("raw samples must be a contiguous CUDA float64 [M][16] tensor")
+        self._check(self.lib.tdde_mlp_fit_skip(self.h, C.c_void_p(raw.data_ptr()), int(raw.shape[0])))
+
+    def set_skip(self, c, sigma):
+        """c: complex [2][4]."""
+        a = np.zeros((2, 4, 2))
+        cc = np.asarray(c)
+        a[..., 0], a[..., 1] = cc.real, cc.imag
+        a = np.ascontiguousarray(a)
+        self._check(self.lib.tdde_mlp_set_skip(self.h, a.ctypes.data_as(C.c_void_p), float(sigma)))
+
+    def get_skip(self):
+        a = np.zeros((2, 4, 2))
+        sig = C.c_double()
+        self._check(self.lib.tdde_mlp_get_skip(self.h, a.ctypes.data_as(C.c_void_p), C.byref(sig)))
+        return a[..., 0] + 1j * a[..., 1], sig.value
 
     def set_pulses(self, pulses):
         batch, nf = len(pulses), len(pulses[0])

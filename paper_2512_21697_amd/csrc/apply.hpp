@@ -75,6 +75,18 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
 
   __syncthreads();
   stage_channel<T>(L.xs, xinst + (size_t)j * cstride, i0, nr, hb);
+  if (op.n_groups > 0) {
+    const int K0 = op.g_first[1];
+    const int p0 = op.g_rowptr[j], p1 = op.g_rowptr[j + 1];
+    bool any = false;
+    for (int q = 0; q < K0; ++q) {
+      const double2 cf = coef_f[op.g_term[q]];
+      any = any || cf.x != 0.0 || cf.y != 0.0;
+    }
+    if (p0 != p1 && any)
+      stage_gather<T>(L.ws, xinst, op.g_col, op.g_val + op.g_voff[0] + (size_t)(p0 - op.g_rowptr[0]) * K0, p0, p1, K0,
+                      i0, nr, hb);
+  }
   __syncthreads();
 
   const T kap = op.kappa[j];
@@ -117,10 +129,13 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
       any = any || cf.x != 0.0 || cf.y != 0.0;
     }
     if (p0 == p1 || !any) continue;  // uniform over the work-group
-    __syncthreads();
-    stage_gather<T>(L.ws, xinst, op.g_col, op.g_val + op.g_voff[gidx] + (size_t)(p0 - rp[0]) * K, p0, p1, K, i0, nr,
-                    hb);
-    __syncthreads();
+    // the first group is staged together with the channel tile above (one barrier less)
+    if (gidx > 0) {
+      __syncthreads();
+      stage_gather<T>(L.ws, xinst, op.g_col, op.g_val + op.g_voff[gidx] + (size_t)(p0 - rp[0]) * K, p0, p1, K, i0, nr,
+                      hb);
+      __syncthreads();
+    }
     if (live) {
       const size_t bstride = (size_t)nb * nr;
       for (int q = 0; q < K; ++q) {

@@ -94,23 +94,24 @@ __device__ inline double2 wg_sum2(double2 v, double* lds) {
 }
 
 // Grid-wide barrier for a co-resident (cooperatively launched) grid.
-// bar[0] = arrival count, bar[1] = generation, bar[2] = error flag. The spin is bounded: on
-// time-out the error flag is raised and every later barrier returns at once, so the kernel
-// always terminates.
+// bar[0] = arrival count, bar[1] = generation, bar[2] = error flag. Arrival is a release (the
+// work-group's writes become visible device-wide, across XCDs); waiting polls with relaxed loads
+// (an acquire per poll would invalidate the XCD's L2 under the working work-groups) and issues one
+// acquire fence after the generation changes. The spin is bounded: on time-out the error flag is
+// raised and every later barrier returns at once, so the kernel always terminates.
 constexpr unsigned kSpinLimit = 1u << 24;
 __device__ inline bool grid_barrier(unsigned* bar, unsigned nwg) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == nwg - 1) {
       __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(2);
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
         if (++spins > kSpinLimit ||
             __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
           __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -118,7 +119,7 @@ __device__ inline bool grid_barrier(unsigned* bar, unsigned nwg) {
         }
       }
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see every arrival's writes (all XCDs)
   }
   __syncthreads();
   return __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;

@@ -29,15 +29,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int H = 256, F = 32;
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + H * F, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H, OFF_W3 = OFF_B2 + H,
-              OFF_B3 = OFF_W3 + 2 * H, OFF_C = OFF_B3 + 2, N_PARAM = OFF_C + 16;
+              OFF_B3 = OFF_W3 + 2 * H, N_PARAM = OFF_B3 + 2;
+constexpr int N_SKIP = 17;     // c[2][4][2] (re, im) and sigma, FP64
 constexpr int RAW = 16;        // doubles per raw training sample
 constexpr int W2P_VEC = 16 * 8 * 64;  // bf16x8 entries of the permuted W2
 
 struct Weights {
   const bf16* W1;       // [H][F]
   const bf16x8* W2p;    // permuted, W2P_VEC entries
-  const float* P;       // FP32 master (biases, W3 rounded copy below, skip c)
+  const float* P;       // FP32 master (biases)
   const float* W3r;     // [2][H] W3 rounded to bf16, as float
+  const double* skip;   // c[2][4][2], sigma
 };
 
 __device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
@@ -231,25 +233,27 @@ __global__ __launch_bounds__(256) void mlp_fwd_kernel(Weights w, FwdArgs a) {
       for (int rt = 0; rt < 2; ++rt) {
         const long r = row0 + 16 * rt + n;
         if (r >= a.M) continue;
-        const float y0 = part[rt][0] + b30, y1 = part[rt][1] + b31;
-        const float* c = w.P + OFF_C + sflag[rt] * 8;
+        const double sig = w.skip[16];
+        const double n0 = (double)(part[rt][0] + b30), n1 = (double)(part[rt][1] + b31);
+        const double* c = w.skip + sflag[rt] * 8;
         if (TRAIN) {
+          // residual of the prediction in units of sigma, formed in FP64: (skip - target) / sigma + y
           const double ir = 1.0 / rho[rt];
-          double o0 = y0, o1 = y1;
+          double l0 = -tgt[rt].x * ir, l1 = -tgt[rt].y * ir;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const double ur = psi[rt][k].x * ir, ui = psi[rt][k].y * ir;
-            o0 += (double)c[2 * k] * ur - (double)c[2 * k + 1] * ui;
-            o1 += (double)c[2 * k] * ui + (double)c[2 * k + 1] * ur;
+            l0 += c[2 * k] * ur - c[2 * k + 1] * ui;
+            l1 += c[2 * k] * ui + c[2 * k + 1] * ur;
           }
-          a.out[r * 2] = (float)o0;
-          a.out[r * 2 + 1] = (float)o1;
+          a.out[r * 2] = (float)(l0 / sig + n0);
+          a.out[r * 2 + 1] = (float)(l1 / sig + n1);
         } else {
-          double g0 = rho[rt] * y0, g1 = rho[rt] * y1;
+          double g0 = rho[rt] * sig * n0, g1 = rho[rt] * sig * n1;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            g0 += (double)c[2 * k] * psi[rt][k].x - (double)c[2 * k + 1] * psi[rt][k].y;
-            g1 += (double)c[2 * k] * psi[rt][k].y + (double)c[2 * k + 1] * psi[rt][k].x;
+            g0 += c[2 * k] * psi[rt][k].x - c[2 * k + 1] * psi[rt][k].y;
+            g1 += c[2 * k] * psi[rt][k].y + c[2 * k + 1] * psi[rt][k].x;
           }
           a.guess[r] = make_double2(g0, g1);
         }
@@ -314,50 +318,173 @@ __global__ void colsum_final_kernel(const float* part, int nchunk, int N, float*
   out[c] = s;
 }
 
-// e = out - t; dY = 2 e / M (fp32 and bf16); per-block partials of the loss and of the skip gradients.
-__global__ __launch_bounds__(256) void loss_kernel(const float* out, const float* T, const float* U, const int* S, long M,
-                                                   float* dY, bf16* dYb, double* part /* [grid][17] */) {
+// out holds the residual e / sigma of every row: L = mean |e / sigma|^2, dL/dy = 2 (e / sigma) / M.
+__global__ __launch_bounds__(256) void loss_kernel(const float* out, long M, float* dY, bf16* dYb, double* part) {
   __shared__ double red[256];
-  double loc[17];
-#pragma unroll
-  for (int k = 0; k < 17; ++k) loc[k] = 0.0;
+  const float gscale = (float)(2.0 / (double)M);
+  double loc = 0.0;
   for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (long)gridDim.x * blockDim.x) {
-    const float e0 = out[2 * r] - T[2 * r], e1 = out[2 * r + 1] - T[2 * r + 1];
-    loc[16] += (double)e0 * e0 + (double)e1 * e1;
-    const float d0 = 2.0f * e0 / (float)M, d1 = 2.0f * e1 / (float)M;
+    const float e0 = out[2 * r], e1 = out[2 * r + 1];
+    loc += (double)e0 * e0 + (double)e1 * e1;
+    const float d0 = gscale * e0, d1 = gscale * e1;
     dY[2 * r] = d0;
     dY[2 * r + 1] = d1;
     dYb[2 * r] = (bf16)d0;
     dYb[2 * r + 1] = (bf16)d1;
-    const int s = S[r];
+  }
+  red[threadIdx.x] = loc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void loss_final_kernel(const double* part, int nblk, double* loss_out, long M) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[b];
+  *loss_out = s / (double)M;
+}
+
+// u_k = psi_{n-k} / rho and the target psi_{n+1} / rho of one raw training row.
+__device__ inline int raw_row(const double* raw, long r, double tau, double2 (&u)[4], double2& t) {
+  const double* p = raw + r * RAW;
+  const double rho = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + p[3] * p[3] + tau * tau);
+  const double ir = 1.0 / rho;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float ur = U[8 * r + 2 * k], ui = U[8 * r + 2 * k + 1];
-      const double gr = (double)d0 * ur + (double)d1 * ui;
-      const double gi = -(double)d0 * ui + (double)d1 * ur;
-      loc[s * 8 + 2 * k] += gr;
-      loc[s * 8 + 2 * k + 1] += gi;
+  for (int k = 0; k < 4; ++k) u[k] = make_double2(p[2 * k] * ir, p[2 * k + 1] * ir);
+  t = make_double2(p[8] * ir, p[9] * ir);
+  return p[12] != 0.0 ? 1 : 0;
+}
+
+// Per-block partials of G_s[k][l] = sum conj(u_k) u_l and r_s[k] = sum conj(u_k) t: [grid][2][20] complex.
+constexpr int kGram = 2 * 20 * 2;
+__global__ __launch_bounds__(256) void gram_kernel(const double* raw, long M, double tau, double* part) {
+  __shared__ double red[256];
+  double loc[kGram];
+#pragma unroll
+  for (int q = 0; q < kGram; ++q) loc[q] = 0.0;
+  for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (long)gridDim.x * blockDim.x) {
+    double2 u[4], t;
+    const int s = raw_row(raw, r, tau, u, t);
+#pragma unroll
+    for (int sv = 0; sv < 2; ++sv) {
+      if (s != sv) continue;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          double2 acc = make_double2(0.0, 0.0);
+          tdde::dot_acc(acc, u[k], u[l]);
+          loc[(sv * 20 + k * 4 + l) * 2] += acc.x;
+          loc[(sv * 20 + k * 4 + l) * 2 + 1] += acc.y;
+        }
+        double2 acc = make_double2(0.0, 0.0);
+        tdde::dot_acc(acc, u[k], t);
+        loc[(sv * 20 + 16 + k) * 2] += acc.x;
+        loc[(sv * 20 + 16 + k) * 2 + 1] += acc.y;
+      }
     }
   }
-  for (int k = 0; k < 17; ++k) {
-    red[threadIdx.x] = loc[k];
+  for (int q = 0; q < kGram; ++q) {
+    red[threadIdx.x] = loc[q];
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
       if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[(long)blockIdx.x * 17 + k] = red[0];
+    if (threadIdx.x == 0) part[(long)blockIdx.x * kGram + q] = red[0];
     __syncthreads();
   }
 }
 
-__global__ void loss_final_kernel(const double* part, int nblk, float* grad_c, double* loss_out, long M) {
-  const int k = threadIdx.x;
-  if (k >= 17) return;
+// Sums the Gram partials in block order and solves G_s c_s = r_s (4x4 complex, partial pivoting).
+__global__ void gram_solve_kernel(const double* part, int nblk, double* skip) {
+  if (threadIdx.x != 0) return;
+  for (int sv = 0; sv < 2; ++sv) {
+    double2 A[4][5];
+    for (int k = 0; k < 4; ++k)
+      for (int l = 0; l < 5; ++l) {
+        const int q = l < 4 ? sv * 20 + k * 4 + l : sv * 20 + 16 + k;
+        double re = 0.0, im = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+          re += part[(long)b * kGram + 2 * q];
+          im += part[(long)b * kGram + 2 * q + 1];
+        }
+        A[k][l] = make_double2(re, im);
+      }
+    for (int col = 0; col < 4; ++col) {
+      int pr = col;
+      double best = 0.0;
+      for (int r = col; r < 4; ++r) {
+        const double v = A[r][col].x * A[r][col].x + A[r][col].y * A[r][col].y;
+        if (v > best) { best = v; pr = r; }
+      }
+      for (int l = 0; l < 5; ++l) { const double2 tmp = A[col][l]; A[col][l] = A[pr][l]; A[pr][l] = tmp; }
+      const double2 piv = A[col][col];
+      const double pd = piv.x * piv.x + piv.y * piv.y;
+      if (pd == 0.0) continue;
+      for (int r = col + 1; r < 4; ++r) {
+        // f = A[r][col] / piv
+        const double2 f = make_double2((A[r][col].x * piv.x + A[r][col].y * piv.y) / pd,
+                                       (A[r][col].y * piv.x - A[r][col].x * piv.y) / pd);
+        for (int l = col; l < 5; ++l) {
+          A[r][l].x -= f.x * A[col][l].x - f.y * A[col][l].y;
+          A[r][l].y -= f.x * A[col][l].y + f.y * A[col][l].x;
+        }
+      }
+    }
+    double2 c[4];
+    for (int k = 3; k >= 0; --k) {
+      double2 v = A[k][4];
+      for (int l = k + 1; l < 4; ++l) {
+        v.x -= A[k][l].x * c[l].x - A[k][l].y * c[l].y;
+        v.y -= A[k][l].x * c[l].y + A[k][l].y * c[l].x;
+      }
+      const double2 piv = A[k][k];
+      const double pd = piv.x * piv.x + piv.y * piv.y;
+      c[k] = pd > 0.0 ? make_double2((v.x * piv.x + v.y * piv.y) / pd, (v.y * piv.x - v.x * piv.y) / pd)
+                      : make_double2(0.0, 0.0);
+    }
+    for (int k = 0; k < 4; ++k) {
+      skip[sv * 8 + 2 * k] = c[k].x;
+      skip[sv * 8 + 2 * k + 1] = c[k].y;
+    }
+  }
+}
+
+// Per-block partials of the squared residual |t - sum_k c[s][k] u_k|^2 of the fitted skip.
+__global__ __launch_bounds__(256) void skip_resid_kernel(const double* raw, long M, double tau, const double* skip,
+                                                         double* part) {
+  __shared__ double red[256];
+  double loc = 0.0;
+  for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < M; r += (long)gridDim.x * blockDim.x) {
+    double2 u[4], t;
+    const int s = raw_row(raw, r, tau, u, t);
+    double e0 = t.x, e1 = t.y;
+    for (int k = 0; k < 4; ++k) {
+      const double cr = skip[s * 8 + 2 * k], ci = skip[s * 8 + 2 * k + 1];
+      e0 -= cr * u[k].x - ci * u[k].y;
+      e1 -= cr * u[k].y + ci * u[k].x;
+    }
+    loc += e0 * e0 + e1 * e1;
+  }
+  red[threadIdx.x] = loc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void skip_sigma_kernel(const double* part, int nblk, long M, double* skip) {
+  if (threadIdx.x != 0) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(long)b * 17 + k];
-  if (k < 16) grad_c[k] = (float)s;
-  else *loss_out = s / (double)M;
+  for (int b = 0; b < nblk; ++b) s += part[b];
+  skip[16] = fmax(sqrt(s / (double)M), 1e-300);
 }
 
 // dZ2 = (dY W3) * silu'(Z2)  (in place over Z2, plus a bf16 copy)
@@ -418,6 +545,7 @@ struct tdde_mlp {
   float *P = nullptr, *G = nullptr, *Mm = nullptr, *Vv = nullptr;
   bf16 *W1b = nullptr, *W2b = nullptr, *W2p = nullptr;
   float* W3r = nullptr;
+  double* skip = nullptr;
   // scratch
   float *out = nullptr, *Z1 = nullptr, *Z2 = nullptr, *U = nullptr, *T = nullptr, *dY = nullptr, *dH = nullptr;
   bf16 *H1 = nullptr, *H2 = nullptr, *X = nullptr, *dYb = nullptr, *dZb = nullptr;
@@ -462,6 +590,7 @@ Weights weights_of(const tdde_mlp* m) {
   w.W2p = reinterpret_cast<const bf16x8*>(m->W2p);
   w.P = m->P;
   w.W3r = m->W3r;
+  w.skip = m->skip;
   return w;
 }
 
@@ -563,7 +692,8 @@ tdde_status tdde_mlp_create(int32_t train_rows, double tau, void* stream, tdde_m
   ALLOC(m->dZb, M * H);
   ALLOC(m->S, M);
   ALLOC(m->gpart, (size_t)(M / kSliceK + 2) * H * H);
-  ALLOC(m->lpart, (size_t)kLossBlocks * 17);
+  ALLOC(m->lpart, (size_t)kLossBlocks * kGram);
+  ALLOC(m->skip, N_SKIP);
   ALLOC(m->loss_dev, 1);
   ALLOC(m->cpart, (size_t)((M + kColRows - 1) / kColRows + 1) * H);
 #undef ALLOC
@@ -571,6 +701,15 @@ tdde_status tdde_mlp_create(int32_t train_rows, double tau, void* stream, tdde_m
       hipMemset(m->Vv, 0, N_PARAM * sizeof(float)) != hipSuccess || hipMemset(m->G, 0, N_PARAM * sizeof(float)) != hipSuccess) {
     tdde_mlp_destroy(m);
     return TDDE_ERR_HIP;
+  }
+  {
+    double sk[N_SKIP] = {0};
+    sk[0] = sk[8] = 1.0;  // previous-state predictor until a fit or set_skip
+    sk[16] = 1.0;
+    if (hipMemcpy(m->skip, sk, sizeof(sk), hipMemcpyHostToDevice) != hipSuccess) {
+      tdde_mlp_destroy(m);
+      return TDDE_ERR_HIP;
+    }
   }
   if (refresh(m) != TDDE_OK || hipDeviceSynchronize() != hipSuccess) {
     tdde_mlp_destroy(m);
@@ -628,10 +767,8 @@ tdde_status tdde_mlp_backward(tdde_mlp* m, const double* raw, int32_t Mi, double
   FwdArgs a = train_args(m, raw, M);
   hipLaunchKernelGGL(mlp_fwd_kernel<true>, dim3(fwd_grid(M)), dim3(256), 0, m->stream, weights_of(m), a);
   MLP_TRY(m, hipGetLastError());
-  hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, m->stream, m->out, m->T, m->U, m->S, M, m->dY, m->dYb,
-                     m->lpart);
-  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, m->stream, m->lpart, kLossBlocks, m->G + OFF_C, m->loss_dev,
-                     M);
+  hipLaunchKernelGGL(loss_kernel, dim3(kLossBlocks), dim3(256), 0, m->stream, m->out, M, m->dY, m->dYb, m->lpart);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, m->stream, m->lpart, kLossBlocks, m->loss_dev, M);
   MLP_TRY(m, hipGetLastError());
   tdde_status s;
   // layer 3: dW3 = dY^T H2, db3 = colsum(dY)
@@ -664,6 +801,39 @@ tdde_status tdde_mlp_adam(tdde_mlp* m, float lr) {
                      lr, bc1, bc2);
   MLP_TRY(m, hipGetLastError());
   return refresh(m);
+}
+
+tdde_status tdde_mlp_fit_skip(tdde_mlp* m, const double* raw, int32_t M) {
+  if (!m || !raw || M <= 0) return TDDE_ERR_ARG;
+  hipLaunchKernelGGL(gram_kernel, dim3(kLossBlocks), dim3(256), 0, m->stream, raw, (long)M, m->tau, m->lpart);
+  hipLaunchKernelGGL(gram_solve_kernel, dim3(1), dim3(64), 0, m->stream, (const double*)m->lpart, kLossBlocks, m->skip);
+  hipLaunchKernelGGL(skip_resid_kernel, dim3(kLossBlocks), dim3(256), 0, m->stream, raw, (long)M, m->tau,
+                     (const double*)m->skip, m->lpart);
+  hipLaunchKernelGGL(skip_sigma_kernel, dim3(1), dim3(64), 0, m->stream, (const double*)m->lpart, kLossBlocks, (long)M,
+                     m->skip);
+  MLP_TRY(m, hipGetLastError());
+  MLP_TRY(m, hipStreamSynchronize(m->stream));
+  return TDDE_OK;
+}
+
+tdde_status tdde_mlp_set_skip(tdde_mlp* m, const double* c, double sigma) {
+  if (!m || !c || !(sigma >= 0.0)) return TDDE_ERR_ARG;
+  double sk[N_SKIP];
+  std::memcpy(sk, c, 16 * sizeof(double));
+  sk[16] = sigma;
+  MLP_TRY(m, hipMemcpyAsync(m->skip, sk, sizeof(sk), hipMemcpyHostToDevice, m->stream));
+  MLP_TRY(m, hipStreamSynchronize(m->stream));
+  return TDDE_OK;
+}
+
+tdde_status tdde_mlp_get_skip(tdde_mlp* m, double* c, double* sigma) {
+  if (!m || !c || !sigma) return TDDE_ERR_ARG;
+  double sk[N_SKIP];
+  MLP_TRY(m, hipMemcpyAsync(sk, m->skip, sizeof(sk), hipMemcpyDeviceToHost, m->stream));
+  MLP_TRY(m, hipStreamSynchronize(m->stream));
+  std::memcpy(c, sk, 16 * sizeof(double));
+  *sigma = sk[16];
+  return TDDE_OK;
 }
 
 tdde_status tdde_mlp_set_pulses(tdde_mlp* m, const tdde_pulse* p, int32_t batch, int32_t nf) {

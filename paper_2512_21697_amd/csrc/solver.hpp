@@ -67,6 +67,17 @@ struct SolveArgs {
   unsigned* bar;          // grid barrier state
   int* counters;          // [n_chunk][kCounterPerStep]
   StatsDev* stats;        // [n_chunk][B] or null
+  unsigned long long* marks;  // optional phase timestamps of work-group 0: (wall clock << 8) | phase
+  int n_marks;
+};
+
+// Phase timestamps (work-group 0, thread 0 only): the timing breakdown of a persistent launch.
+struct Marks {
+  unsigned long long* p;
+  int n, cap;
+  __device__ inline void mark(int id) {
+    if (p != nullptr && blockIdx.x == 0 && threadIdx.x == 0 && n < cap) p[n++] = (wall_clock64() << 8) | (unsigned)id;
+  }
 };
 constexpr int kCounterPerStep = 64;
 
@@ -197,13 +208,13 @@ __device__ inline double chains_own(const SolveArgs& a, const WgInfo& wi, const 
 // r^ = r are already written and their partials (SLOT_RHO, SLOT_RR, SLOT_BB) stored; the
 // unfinished-instance counter *cnt already counts this instance. verify: confirm convergence
 // with the true residual (restart on failure).
-template <typename T>
+template <typename T, bool PREC>
 __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, const c2_t<T>* rhs, size_t base,
-                              double tol, int max_iter, bool verify, int* cnt, Inst& st, Shared& sh) {
+                              double tol, int max_iter, bool verify, int* cnt, Inst& st, Shared& sh, Marks& mk) {
   const DevOp<T>& op = op_of<T>(a);
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<T> ahc = to_c<T>(ah);
-  const bool prec = a.use_prec != 0;
+  constexpr bool prec = PREC;
   c2_t<T>* x = V.x + base;
   c2_t<T>* r = V.r + base;
   c2_t<T>* rh = V.rh + base;
@@ -217,6 +228,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
   while (true) {
     // ---------------- W0
     if (!grid_barrier(a.bar, a.n_wg)) return;
+    mk.mark(10);
     bool work = false;
     double2 beta = make_double2(0.0, 0.0);
     if (wi.live && (st.state == ST_ACTIVE || st.state == ST_PENDING)) {
@@ -260,7 +272,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       }
     }
     if (work) {
-      if (prec) {
+      if constexpr (PREC) {
         chains_own<T>(a, wi, V, base, st.fresh ? MODE_FRESH : MODE_P, beta, st.omega, sh);
       } else {
         const c2_t<T> bc = to_c<T>(beta), oc = to_c<T>(st.omega);
@@ -273,6 +285,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     }
     // ---------------- W1
     if (!grid_barrier(a.bar, a.n_wg)) return;
+    mk.mark(11);
     if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
     if (wi.live && st.state == ST_ACTIVE) {
       double2 acc = make_double2(0.0, 0.0);
@@ -296,6 +309,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     }
     // ---------------- W2
     if (!grid_barrier(a.bar, a.n_wg)) return;
+    mk.mark(12);
     if (wi.live && st.state == ST_ACTIVE) {
       const double2 rv = get_total(a, wi, SLOT_RV, sh);
       if (rv.x == 0.0 && rv.y == 0.0) {
@@ -307,7 +321,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       } else {
         st.alpha = cdiv(st.rho, rv);
         double n2 = 0.0;
-        if (prec) {
+        if constexpr (PREC) {
           n2 = chains_own<T>(a, wi, V, base, MODE_S, st.alpha, st.alpha, sh);
         } else {
           const c2_t<T> al = to_c<T>(st.alpha);
@@ -336,6 +350,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     }
     // ---------------- W3
     if (!grid_barrier(a.bar, a.n_wg)) return;
+    mk.mark(13);
     bool half_done = false;
     if (wi.live && st.state == ST_ACTIVE) {
       const double ss = get_total(a, wi, SLOT_SS, sh).x;
@@ -363,6 +378,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     }
     // ---------------- W4
     if (!grid_barrier(a.bar, a.n_wg)) return;
+    mk.mark(14);
     if (wi.live && st.state == ST_ACTIVE && !half_done) {
       const double2 ts = get_total(a, wi, SLOT_TS, sh);
       const double tt = get_total(a, wi, SLOT_TT, sh).x;
@@ -402,8 +418,10 @@ __device__ inline void fields_to_lds(const SolveArgs& a, const WgInfo& wi, doubl
   __syncthreads();
 }
 
+template <bool PREC, bool MIXED>
 __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
   __shared__ Shared sh;
+  Marks mk{a.marks, 0, a.n_marks};
   WgInfo wi;
   wi.G = a.G;
   wi.live = blockIdx.x < (unsigned)(a.B * a.G);
@@ -417,6 +435,7 @@ __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
     const int step = a.step0 + k;
     int* cnt = a.counters + (size_t)k * kCounterPerStep;
     if (!grid_barrier(a.bar, a.n_wg)) return;
+    mk.mark(1);
     const bool inst = wi.live && (a.mode == MODE_SOLVE || a.n_steps == nullptr || step < a.n_steps[wi.b]);
     WgInfo wk = wi;
     wk.live = inst;
@@ -440,7 +459,7 @@ __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
         double2 bb = {0, 0}, rr = {0, 0};
         const double2* psi = a.psi + base;
         const int gs = a.guess;
-        const bool direct_r = !a.mixed && gs != GUESS_GIVEN;
+        const bool direct_r = !MIXED && gs != GUESS_GIVEN;
         apply_own<double>(a, wk, psi, sh, [&](long e, double2 sx, double2 hx) {
           const double2 bval = cfma<double>(mahc, hx, sx);
           bv[e] = bval;
@@ -456,7 +475,7 @@ __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
             dot_acc(rr, rv, rv);
           }
         });
-        put_partial(a, wk, a.mixed ? SLOT_OBB : SLOT_BB, bb, sh);
+        put_partial(a, wk, MIXED ? SLOT_OBB : SLOT_BB, bb, sh);
         if (direct_r) { put_partial(a, wk, SLOT_RHO, rr, sh); put_partial(a, wk, SLOT_RR, rr, sh); }
         st.matvecs++;
       } else {
@@ -468,23 +487,23 @@ __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
           dot_acc(bb, bval, bval);
           x[e] = a.guess == GUESS_ZERO ? make_double2(0.0, 0.0) : a.x_io[base + e];
         });
-        put_partial(a, wk, a.mixed ? SLOT_OBB : SLOT_BB, bb, sh);
+        put_partial(a, wk, MIXED ? SLOT_OBB : SLOT_BB, bb, sh);
       }
     }
-    const bool need_r = a.mixed || a.guess == GUESS_GIVEN || a.mode == MODE_SOLVE;
+    const bool need_r = MIXED || a.guess == GUESS_GIVEN || a.mode == MODE_SOLVE;
     if (need_r) {
       // r = b - A x0 in FP64 (the outer residual in mixed precision)
       if (!grid_barrier(a.bar, a.n_wg)) return;
       if (inst) {
         double2 rr = {0, 0};
-        double2* rt = a.mixed ? a.r64 + base : V.r + base;
+        double2* rt = MIXED ? a.r64 + base : V.r + base;
         apply_own<double>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
           const double2 rv = csub<double>(bv[e], cfma<double>(ahc, hx, sx));
           rt[e] = rv;
-          if (!a.mixed) V.rh[base + e] = rv;
+          if (!MIXED) V.rh[base + e] = rv;
           dot_acc(rr, rv, rv);
         });
-        if (!a.mixed) {
+        if (!MIXED) {
           put_partial(a, wk, SLOT_RHO, rr, sh);
           put_partial(a, wk, SLOT_RR, rr, sh);
         } else {
@@ -494,9 +513,9 @@ __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
       }
     }
 
-    if (!a.mixed) {
+    if constexpr (!MIXED) {
       if (inst) counter_add(cnt, 1);
-      krylov<double>(a, wk, V, a.bvec, base, a.tol, a.max_iter, true, cnt, st, sh);
+      krylov<double, PREC>(a, wk, V, a.bvec, base, a.tol, a.max_iter, true, cnt, st, sh, mk);
     } else {
       // ---- FP64 iterative refinement around an FP32 BiCGSTAB (inner residuals, dots in FP64)
       KVec<float> U = a.v32;
@@ -549,7 +568,7 @@ __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
         if (__hip_atomic_load(ocnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
         WgInfo wq = wk;
         wq.live = ist.state == ST_ACTIVE;
-        krylov<float>(a, wq, U, a.rhs32, base, a.inner_tol, a.max_iter, false, icnt, ist, sh);
+        krylov<float, PREC>(a, wq, U, a.rhs32, base, a.inner_tol, a.max_iter, false, icnt, ist, sh, mk);
         total_iters += ist.iters;
         total_mv += ist.matvecs;
         // x += ||r|| d (FP64), then r = b - A x (FP64)
@@ -582,6 +601,7 @@ __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
 
     // ---- write back and statistics
     if (!grid_barrier(a.bar, a.n_wg)) return;
+    mk.mark(2);
     if (inst) {
       double2* dst = a.mode == MODE_STEP ? a.psi + base : a.x_io + base;
       elem_own<double>(a, wk, [&](long e) { dst[e] = x[e]; });
@@ -590,14 +610,15 @@ __global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
         o.status = st.state == ST_DONE ? 0 : (st.state == ST_BREAKDOWN ? 2 : 1);
         o.iters = st.iters;
         o.matvecs = st.matvecs;
-        o.restarts = a.mixed ? 0 : st.restarts;
-        o.outer_iters = a.mixed ? st.restarts : 0;
+        o.restarts = MIXED ? 0 : st.restarts;
+        o.outer_iters = MIXED ? st.restarts : 0;
         o.rel_res = st.rel_res;
         o.true_rel_res = st.true_rel_res;
       }
     }
   }
   grid_barrier(a.bar, a.n_wg);
+  mk.mark(3);
 }
 
 }  // namespace tdde

@@ -55,8 +55,21 @@ struct tdde_ctx {
   double* fvals = nullptr;
   PulseDev* pulses = nullptr;
   int* n_steps_dev = nullptr;
-  int n_wg = 0, G = 0;
+  int n_wg = 0, G = 0;          // grid of the variant in use (set per launch)
+  int var_wg[4] = {0, 0, 0, 0};  // co-resident work-groups of each persistent-kernel variant
+  unsigned long long* marks = nullptr;
+  int n_marks = 0;
 };
+
+// persistent kernel variants: index = 2 * mixed + preconditioned
+static const void* persistent_variant(int idx) {
+  switch (idx) {
+    case 0: return reinterpret_cast<const void*>(persistent_kernel<false, false>);
+    case 1: return reinterpret_cast<const void*>(persistent_kernel<true, false>);
+    case 2: return reinterpret_cast<const void*>(persistent_kernel<false, true>);
+    default: return reinterpret_cast<const void*>(persistent_kernel<true, true>);
+  }
+}
 
 static std::string g_create_err;
 
@@ -112,7 +125,10 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(DevOp<T> op, const c2_t
                                                          double2 ah, const double* fvals, int n_fields, int E) {
   __shared__ TileLds<T> L;
   __shared__ double2 coef_f[kMaxTerms];
-  const int it = blockIdx.x, j = blockIdx.y, b = blockIdx.z;
+  // radial tile fastest, then instance, then channel: work-group w runs on XCD w % 8 = tile % 8
+  // (n_itiles a multiple of 8), so every instance and channel of a radial tile shares one L2 and
+  // the instances of one tile run close together (operator bands reused from L2)
+  const int it = blockIdx.x, b = blockIdx.y, j = blockIdx.z;
   if (threadIdx.x < op.n_terms) {
     const double f = fvals[(size_t)b * n_fields + op.t_field[threadIdx.x]];
     const double2 c = op.t_coef[threadIdx.x];
@@ -372,21 +388,21 @@ tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
   if ((s = dev_alloc(c, &c->fvals, (size_t)c->d.batch * c->d.n_fields)) != TDDE_OK) return s;
   if ((s = dev_alloc(c, &c->pulses, (size_t)c->d.batch * c->d.n_fields)) != TDDE_OK) return s;
   if ((s = dev_alloc(c, &c->n_steps_dev, (size_t)c->d.batch)) != TDDE_OK) return s;
-  // persistent grid: as many work-groups as can be co-resident
-  int dev = 0, ncu = 0, per_cu = 0;
+  // persistent grids: as many work-groups as can be co-resident, per kernel variant
+  int dev = 0, ncu = 0, max_wg = 0;
   HIP_TRY(c, hipGetDevice(&dev));
   HIP_TRY(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(persistent_kernel),
-                                                          kThreads, 0));
-  if (per_cu <= 0) return fail(c, TDDE_ERR_HIP, "persistent kernel cannot be resident");
-  per_cu = std::min(per_cu, 4);
-  int n_wg = ncu * per_cu;
-  if (c->d.batch > n_wg) return fail(c, TDDE_ERR_ARG, "batch larger than the co-resident work-group count");
-  c->G = n_wg / c->d.batch;
-  // multiple of 8 work-groups per instance keeps a tile of every instance on one XCD
-  if (c->G >= 8) c->G -= c->G % 8;
-  c->n_wg = n_wg;
-  if ((s = dev_alloc(c, &c->part, (size_t)c->d.batch * c->G * kSlots)) != TDDE_OK) return s;
+  for (int v = 0; v < 4; ++v) {
+    int per_cu = 0;
+    HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_variant(v), kThreads, 0));
+    if (per_cu <= 0) return fail(c, TDDE_ERR_HIP, "persistent kernel cannot be resident");
+    c->var_wg[v] = ncu * std::min(per_cu, 4);
+    if (c->d.batch > c->var_wg[v]) return fail(c, TDDE_ERR_ARG, "batch larger than the co-resident work-group count");
+    max_wg = std::max(max_wg, c->var_wg[v]);
+  }
+  c->n_wg = c->var_wg[0];
+  c->G = c->n_wg / c->d.batch;
+  if ((s = dev_alloc(c, &c->part, (size_t)max_wg * kSlots)) != TDDE_OK) return s;
   if ((s = dev_alloc(c, &c->bar, 4)) != TDDE_OK) return s;
   c->n_counters = 64 * kCounterPerStep;
   if ((s = dev_alloc(c, &c->counters, (size_t)c->n_counters)) != TDDE_OK) return s;
@@ -394,6 +410,26 @@ tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
   if ((s = dev_alloc(c, &c->stats_dev, (size_t)c->stats_cap)) != TDDE_OK) return s;
   HIP_TRY(c, hipDeviceSynchronize());
   c->assembled = true;
+  return TDDE_OK;
+}
+
+tdde_status tdde_debug_phase_marks(tdde_ctx* c, int32_t cap) {
+  if (!c || cap < 0) return fail(c, TDDE_ERR_ARG, "bad argument");
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  if (cap > c->n_marks) {
+    tdde_status s = dev_alloc(c, &c->marks, (size_t)cap);
+    if (s != TDDE_OK) return s;
+  }
+  if (cap == 0) c->marks = nullptr;
+  c->n_marks = cap;
+  return TDDE_OK;
+}
+
+tdde_status tdde_debug_read_marks(tdde_ctx* c, uint64_t* host, int32_t cap) {
+  if (!c || !host || cap < 0) return fail(c, TDDE_ERR_ARG, "bad argument");
+  if (!c->marks) return fail(c, TDDE_ERR_STATE, "enable phase marks first");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(host, c->marks, (size_t)std::min(cap, c->n_marks) * sizeof(uint64_t), hipMemcpyDeviceToHost));
   return TDDE_OK;
 }
 
@@ -568,7 +604,7 @@ static tdde_status launch_apply(tdde_ctx* c, const DevOp<T>& op, tdde_c128 as, t
   if (!c || !x || !y) return fail(c, TDDE_ERR_ARG, "null argument");
   if (!c->assembled || !c->field_set) return fail(c, TDDE_ERR_STATE, "assemble and set_field first");
   if (x == y) return fail(c, TDDE_ERR_ARG, "x and y must differ");
-  dim3 grid(op.n_itiles, c->d.nang, c->d.batch);
+  dim3 grid(op.n_itiles, c->d.batch, c->d.nang);
   hipLaunchKernelGGL(apply_kernel<T>, grid, dim3(kThreads), 0, c->stream, op, (const c2_t<T>*)x, (c2_t<T>*)y,
                      make_double2(as.re, as.im), make_double2(ah.re, ah.im), (const double*)c->fvals, c->d.n_fields,
                      c->E);
@@ -606,13 +642,25 @@ static tdde_status check_opts(tdde_ctx* c, const tdde_solve_opts* o) {
 
 static tdde_status run_persistent(tdde_ctx* c, SolveArgs& a, int n_chunk) {
   if (n_chunk > 64) return fail(c, TDDE_ERR_ARG, "at most 64 steps per launch");
+  const int v = 2 * (a.mixed ? 1 : 0) + (a.use_prec ? 1 : 0);
+  // work-groups per instance: a multiple of 8 keeps a tile of every instance on one XCD
+  int G = c->var_wg[v] / c->d.batch;
+  if (G >= 8) G -= G % 8;
+  c->n_wg = c->var_wg[v];
+  c->G = G;
+  a.n_wg = c->n_wg;
+  a.G = G;
+  a.marks = c->marks;
+  a.n_marks = c->n_marks;
   hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->counters),
                      c->n_counters);
   hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, c->stream, c->bar, 4);
+  if (c->marks)
+    hipLaunchKernelGGL(zero_words, dim3(16), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->marks),
+                       2 * c->n_marks);
   HIP_TRY(c, hipGetLastError());
   void* args[] = {&a};
-  HIP_TRY(c, hipLaunchCooperativeKernel(reinterpret_cast<const void*>(persistent_kernel), dim3(c->n_wg),
-                                        dim3(kThreads), args, 0, c->stream));
+  HIP_TRY(c, hipLaunchCooperativeKernel(persistent_variant(v), dim3(c->n_wg), dim3(kThreads), args, 0, c->stream));
   return TDDE_OK;
 }
 
@@ -629,9 +677,7 @@ static SolveArgs base_args(tdde_ctx* c, const tdde_solve_opts* o) {
   a.r64 = c->r64;
   a.rhs32 = c->rhs32;
   a.B = c->d.batch;
-  a.G = c->G;
   a.E = c->E;
-  a.n_wg = c->n_wg;
   a.guess = o->guess;
   a.mixed = o->precision == TDDE_PREC_MIXED;
   a.max_iter = o->max_iter;

@@ -23,8 +23,8 @@ HIDDEN, N_FEAT = 256, 32
 
 
 def init_params(seed: int, n_params: int) -> np.ndarray:
-    """Uniform fan-in initialisation of W1, W2 and a zero last layer; the skip path starts as the
-    previous-state predictor (c[s][0] = 1)."""
+    """Uniform fan-in initialisation of W1, W2 and a zero last layer (the network starts as the
+    fitted skip alone)."""
     rng = np.random.default_rng(seed)
     p = []
     p.append(rng.uniform(-1, 1, (HIDDEN, N_FEAT)) * math.sqrt(3.0 / 11.0))  # W1 (11 live features)
@@ -33,9 +33,6 @@ def init_params(seed: int, n_params: int) -> np.ndarray:
     p.append(np.zeros(HIDDEN))  # b2
     p.append(np.zeros((2, HIDDEN)))  # W3
     p.append(np.zeros(2))  # b3
-    c = np.zeros((2, 4, 2))
-    c[:, 0, 0] = 1.0
-    p.append(c)
     flat = np.concatenate([a.ravel() for a in p]).astype(np.float32)
     assert flat.size == n_params
     return flat
@@ -97,7 +94,9 @@ def collect_samples(torch, op, pulses, n_steps, psi0, dt, t0=0.0, every=20, rows
 
 
 def train(torch, net: Net, raw, n_iter=1500, batch_rows=8192, lr=1e-3, seed=0, log=None):
-    """Minibatch Adam on the GPU; returns the loss history."""
+    """Least-squares skip on all rows, then minibatch Adam on the GPU; returns the loss history
+    (in units of the skip's residual)."""
+    net.fit_skip(raw)
     gen = torch.Generator(device=raw.device)
     gen.manual_seed(seed)
     M = raw.shape[0]
@@ -114,7 +113,8 @@ def train(torch, net: Net, raw, n_iter=1500, batch_rows=8192, lr=1e-3, seed=0, l
 
 
 def propagate(torch, op, pulses, n_steps, psi0, dt, mode, net: Net | None = None, t0=0.0, chunk=32):
-    """Run every instance to its own length with guess mode "zero", "prev" or "mlp".
+    """Run every instance to its own length with guess mode "zero", "prev", "skip" (the network's
+    fitted linear part alone) or "mlp" (the whole network).
 
     Returns (final states [B*E] tensor, per-step stats array [steps][B], elapsed seconds)."""
     B = len(pulses)
@@ -137,9 +137,12 @@ def propagate(torch, op, pulses, n_steps, psi0, dt, mode, net: Net | None = None
             k = min(chunk, total - n)
             s.run_batched(psi, t0, n, k, ns, opts, stats[n * sz:(n + k) * sz])
             n += k
-    elif mode == "mlp":
+    elif mode in ("mlp", "skip"):
         assert net is not None
         net.set_pulses(pulses)
+        c_saved, sig_saved = net.get_skip()
+        if mode == "skip":
+            net.set_skip(c_saved, 0.0)
         opts = solve_opts(tol=1e-12, max_iter=300, guess=GUESS_GIVEN)
         hist = [psi.clone() for _ in range(4)]
         guess = torch.empty_like(psi)
@@ -149,6 +152,8 @@ def propagate(torch, op, pulses, n_steps, psi0, dt, mode, net: Net | None = None
             last = hist.pop()
             last.copy_(psi)
             hist.insert(0, last)
+        if mode == "skip":
+            net.set_skip(c_saved, sig_saved)
     else:
         raise ValueError(mode)
     torch.cuda.synchronize()

