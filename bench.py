@@ -57,12 +57,15 @@ def prec_factor_bytes(op):
     return nblk * (n * (2 * w + 1) + 2 * P * w * w) * 16
 
 
-def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64):
-    """Run warmup + timed steps in persistent chunks; returns (ms_per_step, stats array, kernel_ms_list)."""
+def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0):
+    """Run warmup + timed steps in persistent chunks.
+
+    Returns (ms_per_step, stats array, [(kernel ms, steps) per launch], wall seconds, final state)."""
     s = P.Solver(w.op, 1)
     s.set_dt(w.dt)
     s.set_pulses(w.pulses)
-    opts = P.solve_opts(tol=1e-12, max_iter=200, guess=guess, precond=precond)
+    opts = P.solve_opts(tol=1e-12, max_iter=200, guess=guess, precond=precond, precision=precision, inner_tol=1e-5,
+                        max_outer=20)
     psi = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
     stream = torch.cuda.current_stream()
     total = warmup + steps
@@ -96,7 +99,77 @@ def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64):
     launches = [(a.elapsed_time(b), n) for a, b, n in evs]
     st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
     s.close()
-    return ms / steps, st[warmup:], launches, wall
+    return ms / steps, st[warmup:], launches, wall, psi
+
+
+def s_norm(P, torch, op, psi):
+    """psi^H S psi with the library's apply (S x: a_s = 1, a_h = 0)."""
+    s = P.Solver(op, 1)
+    s.set_field(np.zeros((1, op.n_fields)))
+    y = torch.empty_like(psi)
+    s.apply(psi, y, 1.0, 0.0)
+    torch.cuda.synchronize()
+    s.close()
+    return float(torch.vdot(psi, y).real.item())
+
+
+def mixed_section(P, torch, w, steps, warmup, psi64):
+    """FP32-inner / FP64-refinement solve on the hydrogen operator vs the FP64 path (same steps)."""
+    ms, st, launches, wall, psi = run_gpu_steps(P, torch, w, steps, warmup, precond=1, guess=P.GUESS_PREV,
+                                                precision=P.PREC_MIXED)
+    diff = float(torch.linalg.vector_norm(psi - psi64).item() / torch.linalg.vector_norm(psi64).item())
+    n0 = s_norm(P, torch, w.op, torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0"))
+    n1 = s_norm(P, torch, w.op, psi)
+    return {"ms_per_step": ms, "steps_per_s": 1000.0 / ms, "outer_iters_per_step": float(st["outer_iters"].mean()),
+            "inner_iters_per_step": float(st["iters"].mean()), "all_converged": bool(np.all(st["status"] == 0)),
+            "max_true_rel_res": float(st["true_rel_res"].max()),
+            "state_rel_diff_vs_fp64_after_steps": diff, "s_norm_drift": abs(n1 - n0)}
+
+
+def batched_learned_section(P, torch, train_steps, eval_steps, n_train=200, train_batch=50, log=None):
+    """Batched sweep (64 instances of the block-banded recipe at Nr = 2000, Nang = 41) with zero,
+    previous-state, fitted-skip and full-network guesses; the network is trained on solver
+    trajectories of n_train other pulses."""
+    from paper_2512_21697_amd import learned
+    from workloads import synthetic
+    w5 = synthetic.config5()
+    op = w5.op
+    psi0 = w5.psi0[0]
+    rows = []
+    t0 = time.perf_counter()
+    for k in range(0, n_train, train_batch):
+        seeds = list(range(1 + k, 1 + min(n_train, k + train_batch)))
+        tp, tn = synthetic.batched_pulses(seeds)
+        tn = np.minimum(tn, train_steps)
+        rows.append(learned.collect_samples(torch, op, tp, tn, np.repeat(psi0[None], len(seeds), 0), w5.dt, every=10,
+                                            rows_per_instance=128, seed=k))
+        if log:
+            log(f"bench: collected trajectories {k + len(seeds)}/{n_train}")
+    raw = torch.cat(rows, 0)
+    t_collect = time.perf_counter() - t0
+    net = P.Net(16384, 1e-6)
+    net.set_params(learned.init_params(0, net.n_params))
+    t0 = time.perf_counter()
+    losses = learned.train(torch, net, raw, n_iter=800, batch_rows=16384, lr=1e-3)
+    t_train = time.perf_counter() - t0
+    ns = np.minimum(w5.n_steps, eval_steps)
+    out = {"instances": int(w5.batch), "train_rows": int(raw.shape[0]), "collect_s": t_collect, "train_s": t_train,
+           "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-50:].mean()),
+           "skip_sigma": float(net.get_skip()[1])}
+    ref = None
+    for mode in ("zero", "prev", "skip", "mlp"):
+        fin, st, el = learned.propagate(torch, op, w5.pulses, ns, w5.psi0, w5.dt, mode, net=net)
+        act = learned.active_mask(ns, st.shape[0])
+        if ref is None:
+            ref = fin
+        d = float(torch.linalg.vector_norm(fin - ref).item() / torch.linalg.vector_norm(ref).item())
+        out[mode] = {"iters_per_step": float(st["iters"][act].mean()), "instance_steps_per_s": float(act.sum() / el),
+                     "batched_steps_per_s": float(st.shape[0] / el), "all_converged": bool(np.all(st["status"][act] == 0)),
+                     "rel_diff_vs_zero_guess": d}
+        if log:
+            log(f"bench: batched {mode}: {out[mode]}")
+    net.close()
+    return out
 
 
 def spmv_measure(P, torch, w, reps=20):
@@ -147,6 +220,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the beyond-dipole apply measurement")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched learned-guess comparison")
+    ap.add_argument("--batched-steps", type=int, default=200, help="steps per instance in the batched sections")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -164,8 +240,8 @@ def main():
     w = dkb.config2()
     E = w.op.n_unknowns
     _log(f"bench: gpu steps={args.steps} warmup={args.warmup}")
-    ms_step, st, launches, wall = run_gpu_steps(P, torch, w, args.steps, args.warmup, precond=1,
-                                                guess=P.GUESS_PREV)
+    ms_step, st, launches, wall, psi64 = run_gpu_steps(P, torch, w, args.steps, args.warmup, precond=1,
+                                                       guess=P.GUESS_PREV)
     iters = st["iters"].astype(float)
     mv = st["matvecs"].astype(float)
     ok = bool(np.all(st["status"] == 0))
@@ -202,6 +278,12 @@ def main():
                      "kernel": "persistent_kernel", "kernel_ms_per_launch": kern_ms,
                      "steps_per_launch": steps_per_launch, "alg_bytes_per_step": bytes_step},
     }
+    if not args.no_mixed:
+        _log("bench: mixed precision on the hydrogen operator")
+        res["mixed_precision"] = mixed_section(P, torch, w, args.steps, args.warmup, psi64)
+    if not args.no_batched:
+        _log("bench: batched sweep, learned vs plain guesses")
+        res["batched_learned"] = batched_learned_section(P, torch, args.batched_steps, args.batched_steps, log=_log)
     if not args.no_extra:
         _log("bench: beyond-dipole apply (Nr=4000, Nang=770, N=6.16e6)")
         w3 = synthetic.config3()

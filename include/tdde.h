@@ -57,7 +57,7 @@ typedef struct tdde_ctx tdde_ctx; /* opaque; use one context per stream / host t
 typedef struct {
   int32_t nr;        /* radial functions per component (B-spline count after boundary trim) */
   int32_t nang;      /* angular channels (kappa, mu)                                         */
-  int32_t half_band; /* radial half-bandwidth hb (order-7 B-splines: 6)                      */
+  int32_t half_band; /* radial half-bandwidth hb; must be 6 (order-7 B-splines, Sec. 2.2)     */
   int32_t batch;     /* independent instances sharing the operator (different fields)        */
   int32_t n_fields;  /* time functions per instance                                          */
 } tdde_dims;
@@ -121,7 +121,7 @@ typedef struct {
 } tdde_solve_stats;
 
 /* Create a context for the given sizes on `hip_stream` (hipStream_t or NULL). Allocates nothing
- * on the device. Errors: TDDE_ERR_ARG for nonpositive sizes or half_band > 8. */
+ * on the device. Errors: TDDE_ERR_ARG for nonpositive sizes, half_band != 6 or n_fields > 16. */
 tdde_status tdde_create(const tdde_dims* dims, void* hip_stream, tdde_ctx** out);
 
 /* Copy the operator to the device (FP64 and FP32 copies) and allocate every workspace buffer.

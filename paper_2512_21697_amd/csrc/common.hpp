@@ -8,7 +8,8 @@ namespace tdde {
 
 constexpr int kThreads = 256;    // work-group size of every kernel
 constexpr int kTileR = 128;      // radial points per tile (x 2 spinor components = 256 threads)
-constexpr int kMaxHB = 8;        // largest supported radial half-bandwidth
+constexpr int kHB = 6;           // radial half-bandwidth: order-7 B-splines overlap 6 neighbours per side
+constexpr int kMaxHB = kHB;
 constexpr int kMaxTerms = 32;    // largest number of coupling terms
 constexpr int kMaxGroup = 8;     // coupling terms staged together (same angular sparsity pattern)
 constexpr int kMaxFields = 16;   // largest number of time functions per instance

@@ -40,8 +40,8 @@ __device__ inline size_t prow(int q, int nr) { return (size_t)(q & 1) * nr + (q 
 // Input of the lower solve, formed on the fly and written back:
 //   MODE_P:  z = r + beta (p - omega v)   (BiCGSTAB direction update; z is stored into p)
 //   MODE_S:  z = r - alpha v              (BiCGSTAB half step;        z is stored into s)
-//   MODE_IN: z = in                       (plain preconditioner apply)
-enum { MODE_P = 0, MODE_S = 1, MODE_IN = 2, MODE_FRESH = 3 /* z = r, stored into p */ };
+//   MODE_IN, MODE_IN_S: z = in            (plain preconditioner apply; input not rewritten)
+enum { MODE_P = 0, MODE_S = 1, MODE_IN = 2, MODE_FRESH = 3 /* z = r, stored into p */, MODE_IN_S = 4 /* z = s */ };
 
 template <typename T> struct ChainIO {
   const c2_t<T>* r;   // residual (channel base)
@@ -66,7 +66,7 @@ __device__ inline c2_t<T> chain_input(const ChainIO<T>& io, size_t e, bool store
   } else {
     z = io.pz[e];
   }
-  if (store && io.mode != MODE_IN) io.pz[e] = z;
+  if (store && io.mode != MODE_IN && io.mode != MODE_IN_S) io.pz[e] = z;
   return z;
 }
 

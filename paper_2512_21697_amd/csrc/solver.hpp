@@ -13,8 +13,9 @@
 // enabled) runs in five windows separated by grid barriers:
 //   W0  rho, ||r|| -> convergence / restart decision, beta;  p = r + beta (p - omega v), p^ = K^-1 p
 //   W1  v = A p^, <r^, v>              (VERIFY instances: r = b - A x, ||r||)
-//   W2  alpha;  s = r - alpha v, s^ = K^-1 s, ||s||   (VERIFY: accept or restart)
-//   W3  ||s|| test (half step);  t = A s^, <t, s>, <t, t>
+//   W2  alpha;  s = r - alpha v, ||s||   (VERIFY: accept or restart)
+//   W3  ||s|| test (half step);  without preconditioner t = A s, <t, s>, <t, t>; with it s^ = K^-1 s
+//   W3b (preconditioned only) t = A s^, <t, s>, <t, t>
 //   W4  omega;  x += alpha p^ + omega s^,  r = s - omega t,  <r^, r>, ||r||
 // The loop ends when the count of unfinished instances, read right after the W1 barrier, is zero.
 #pragma once
@@ -192,8 +193,9 @@ __device__ inline double chains_own(const SolveArgs& a, const WgInfo& wi, const 
       ChainIO<T> io;
       io.r = V.r + cb;
       io.v = V.v + cb;
-      io.pz = (mode == MODE_S ? V.s : V.p) + cb;
-      io.out = (mode == MODE_S ? V.sh : V.ph) + cb;
+      const bool on_s = mode == MODE_S || mode == MODE_IN_S;
+      io.pz = (on_s ? V.s : V.p) + cb;
+      io.out = (on_s ? V.sh : V.ph) + cb;
       io.c1 = c1;
       io.c2 = c2;
       io.mode = mode;
@@ -320,17 +322,15 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         put_partial(a, wi, SLOT_AUX, acc, sh);
       } else {
         st.alpha = cdiv(st.rho, rv);
+        // s = r - alpha v and ||s||^2; the preconditioned s^ is formed only if the half step does
+        // not already converge (next window)
         double n2 = 0.0;
-        if constexpr (PREC) {
-          n2 = chains_own<T>(a, wi, V, base, MODE_S, st.alpha, st.alpha, sh);
-        } else {
-          const c2_t<T> al = to_c<T>(st.alpha);
-          elem_own<T>(a, wi, [&](long e) {
-            const c2_t<T> sv = csub<T>(r[e], cmul<T>(al, v[e]));
-            s[e] = sv;
-            n2 += (double)sv.x * sv.x + (double)sv.y * sv.y;
-          });
-        }
+        const c2_t<T> al = to_c<T>(st.alpha);
+        elem_own<T>(a, wi, [&](long e) {
+          const c2_t<T> sv = csub<T>(r[e], cmul<T>(al, v[e]));
+          s[e] = sv;
+          n2 += (double)sv.x * sv.x + (double)sv.y * sv.y;
+        });
         put_partial(a, wi, SLOT_SS, make_double2(n2, 0.0), sh);
       }
     } else if (wi.live && st.state == ST_VERIFY) {
@@ -363,9 +363,28 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         st.state = verify ? ST_VERIFY : ST_DONE;
         if (!verify) { st.true_rel_res = st.rel_res; counter_add(cnt, -1); }
         half_done = true;
+      } else if constexpr (PREC) {
+        chains_own<T>(a, wi, V, base, MODE_IN_S, st.alpha, st.alpha, sh);  // s^ = K^-1 s
       } else {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
-        apply_own<T>(a, wi, prec ? shv : s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        apply_own<T>(a, wi, s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+          const c2_t<T> tv = cfma<T>(ahc, hx, sx);
+          t[e] = tv;
+          dot_acc(ts, tv, s[e]);
+          dot_acc(tt, tv, tv);
+        });
+        put_partial(a, wi, SLOT_TS, ts, sh);
+        put_partial(a, wi, SLOT_TT, tt, sh);
+        st.matvecs++;
+      }
+    }
+    if constexpr (PREC) {
+      // ---------------- W3b: t = A s^
+      if (!grid_barrier(a.bar, a.n_wg)) return;
+      mk.mark(15);
+      if (wi.live && st.state == ST_ACTIVE && !half_done) {
+        double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
+        apply_own<T>(a, wi, shv, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
           const c2_t<T> tv = cfma<T>(ahc, hx, sx);
           t[e] = tv;
           dot_acc(ts, tv, s[e]);
@@ -419,7 +438,8 @@ __device__ inline void fields_to_lds(const SolveArgs& a, const WgInfo& wi, doubl
 }
 
 template <bool PREC, bool MIXED>
-__global__ __launch_bounds__(kThreads) void persistent_kernel(SolveArgs a) {
+__global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(PREC ? 2 : 4)))
+void persistent_kernel(SolveArgs a) {
   __shared__ Shared sh;
   Marks mk{a.marks, 0, a.n_marks};
   WgInfo wi;

@@ -200,9 +200,9 @@ const char* tdde_last_error(const tdde_ctx* ctx) { return ctx ? ctx->err.c_str()
 tdde_status tdde_create(const tdde_dims* dims, void* hip_stream, tdde_ctx** out) {
   if (!dims || !out) { g_create_err = "null argument"; return TDDE_ERR_ARG; }
   *out = nullptr;
-  if (dims->nr <= 0 || dims->nang <= 0 || dims->half_band < 0 || dims->half_band > kMaxHB || dims->batch <= 0 ||
-      dims->n_fields <= 0 || dims->n_fields > kMaxFields) {
-    g_create_err = "dims out of range (nr, nang, batch > 0; 0 <= half_band <= 8; 1 <= n_fields <= 16)";
+  if (dims->nr <= 0 || dims->nang <= 0 || dims->half_band != kHB || dims->batch <= 0 || dims->n_fields <= 0 ||
+      dims->n_fields > kMaxFields) {
+    g_create_err = "dims out of range (nr, nang, batch > 0; half_band == 6; 1 <= n_fields <= 16)";
     return TDDE_ERR_ARG;
   }
   if ((double)dims->nr * dims->nang * 2 > 2.0e9) { g_create_err = "instance too large"; return TDDE_ERR_ARG; }
