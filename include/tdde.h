@@ -110,7 +110,8 @@ typedef struct {
 
 /* Per-instance statistics of one solve / step. */
 typedef struct {
-  int32_t status;       /* tdde_status of this instance                                       */
+  int32_t status;       /* tdde_status of this instance; TDDE_ERR_HIP if the launch's grid     */
+                        /* barrier timed out before the step finished (step not completed)     */
   int32_t iters;        /* BiCGSTAB iterations (a converged half iteration counts as one)     */
   int32_t matvecs;      /* operator applications, residual checks included                     */
   int32_t restarts;     /* breakdown or failed true-residual restarts                          */

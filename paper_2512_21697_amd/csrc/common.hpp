@@ -77,53 +77,95 @@ template <typename T> struct DevOp {
   const double2* t_coef;       // [n_terms] (double even for the FP32 copy)
 };
 
-// Sum of a double over the work-group (fixed order: wave shuffles, then waves in order).
-__device__ inline double wg_sum(double v, double* lds) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+// Sum over the work-group of a complex (two doubles), fixed order: wave shuffles, then waves in
+// order. lds holds 2 * kThreads / 64 doubles.
+__device__ inline double2 wg_sum2(double2 v, double* lds) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
+  }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) { lds[2 * wid] = v.x; lds[2 * wid + 1] = v.y; }
   __syncthreads();
-  if (lane == 0) lds[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int k = 0; k < kThreads / 64; ++k) s += lds[k];
+  double2 s = make_double2(0.0, 0.0);
+  for (int k = 0; k < kThreads / 64; ++k) { s.x += lds[2 * k]; s.y += lds[2 * k + 1]; }
   __syncthreads();
   return s;
 }
 
-__device__ inline double2 wg_sum2(double2 v, double* lds) {
-  return make_double2(wg_sum(v.x, lds), wg_sum(v.y, lds));
-}
-
 // Grid-wide barrier for a co-resident (cooperatively launched) grid.
-// bar[0] = arrival count, bar[1] = generation, bar[2] = error flag. Arrival is a release (the
-// work-group's writes become visible device-wide, across XCDs); waiting polls with relaxed loads
-// (an acquire per poll would invalidate the XCD's L2 under the working work-groups) and issues one
-// acquire fence after the generation changes. The spin is bounded: on time-out the error flag is
-// raised and every later barrier returns at once, so the kernel always terminates.
+//
+// Arrivals are spread over kBarGroups counters (work-group g arrives on counter g % kBarGroups),
+// each in its own 256-byte line, so no more than nwg / kBarGroups atomics queue on one address;
+// the last arrival of a group arrives on the top counter, and the last of those publishes the new
+// generation into one flag line per group, which that group's work-groups poll. Counters are reset
+// by their last arrival before the generation is published, so the next barrier finds them at zero.
+// Ordering: arrival is a release (the work-group's writes become visible device-wide, across
+// XCDs); the group and top finishers acquire before passing on; pollers use relaxed loads (an
+// acquire per poll would invalidate the XCD's L2 under the working work-groups) and one acquire
+// fence once the generation has changed. The spin is bounded: on time-out the error word is set
+// and every later barrier returns false at once, so the kernel always terminates.
+constexpr int kBarGroups = 16;
+constexpr int kBarLine = 64;  // words per 256-byte line
+constexpr int kBarTop = kBarGroups * kBarLine;
+constexpr int kBarFlag0 = (kBarGroups + 1) * kBarLine;
+constexpr int kBarErr = (2 * kBarGroups + 1) * kBarLine;
+constexpr int kBarWords = (2 * kBarGroups + 2) * kBarLine;  // zeroed before every launch
 constexpr unsigned kSpinLimit = 1u << 24;
-__device__ inline bool grid_barrier(unsigned* bar, unsigned nwg) {
+
+struct GridBar {
+  unsigned* w;     // kBarWords words
+  unsigned nwg;    // work-groups in the grid
+  unsigned gen;    // generations passed (all threads keep the same count)
+  bool failed;
+};
+
+__device__ inline bool grid_barrier(GridBar& gb) {
+  __shared__ unsigned bar_ok;
+  if (gb.failed) return false;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nwg - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    unsigned* w = gb.w;
+    const unsigned K = gb.nwg < (unsigned)kBarGroups ? gb.nwg : (unsigned)kBarGroups;
+    const unsigned g = blockIdx.x % K;
+    const unsigned members = (gb.nwg - g + K - 1) / K;
+    const unsigned target = gb.gen + 1;
+    unsigned ok = 1;
+    const unsigned a = __hip_atomic_fetch_add(&w[g * kBarLine], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    bool publish = false;
+    if (a == members - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(&w[g * kBarLine], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned t = __hip_atomic_fetch_add(&w[kBarTop], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == K - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_store(&w[kBarTop], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        for (unsigned k = 0; k < K; ++k)
+          __hip_atomic_store(&w[kBarFlag0 + k * kBarLine], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        publish = true;
+      }
+    }
+    if (!publish) {
       unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(&w[kBarFlag0 + g * kBarLine], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit ||
-            __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ++spins;
+        if ((spins & 255u) == 0 &&
+            (spins > kSpinLimit || __hip_atomic_load(&w[kBarErr], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+          __hip_atomic_store(&w[kBarErr], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
           break;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see every arrival's writes (all XCDs)
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see every arrival's writes (all XCDs)
+    bar_ok = ok;
   }
   __syncthreads();
-  return __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+  gb.gen++;
+  if (bar_ok == 0u) gb.failed = true;
+  return !gb.failed;
 }
 
 // Time function of eq. ndpPot (dipole limit): amp * env * sin(omega t + phase) on (0, T).

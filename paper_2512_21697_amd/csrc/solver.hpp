@@ -102,7 +102,7 @@ struct Shared {
     SharedLds<double> d;
     SharedLds<float> f;
   } u;
-  double red[kThreads / 64];
+  double red[2 * kThreads / 64];
   double2 coef_f[kMaxTerms];
 };
 
@@ -212,7 +212,8 @@ __device__ inline double chains_own(const SolveArgs& a, const WgInfo& wi, const 
 // with the true residual (restart on failure).
 template <typename T, bool PREC>
 __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, const c2_t<T>* rhs, size_t base,
-                              double tol, int max_iter, bool verify, int* cnt, Inst& st, Shared& sh, Marks& mk) {
+                              double tol, int max_iter, bool verify, int* cnt, Inst& st, Shared& sh, Marks& mk,
+                              GridBar& gb) {
   const DevOp<T>& op = op_of<T>(a);
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<T> ahc = to_c<T>(ah);
@@ -229,7 +230,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
   const c2_t<T>* b_ = rhs + base;
   while (true) {
     // ---------------- W0
-    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (!grid_barrier(gb)) return;
     mk.mark(10);
     bool work = false;
     double2 beta = make_double2(0.0, 0.0);
@@ -286,7 +287,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       st.fresh = 0;
     }
     // ---------------- W1
-    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (!grid_barrier(gb)) return;
     mk.mark(11);
     if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
     if (wi.live && st.state == ST_ACTIVE) {
@@ -310,7 +311,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       st.matvecs++;
     }
     // ---------------- W2
-    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (!grid_barrier(gb)) return;
     mk.mark(12);
     if (wi.live && st.state == ST_ACTIVE) {
       const double2 rv = get_total(a, wi, SLOT_RV, sh);
@@ -349,7 +350,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       }
     }
     // ---------------- W3
-    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (!grid_barrier(gb)) return;
     mk.mark(13);
     bool half_done = false;
     if (wi.live && st.state == ST_ACTIVE) {
@@ -380,7 +381,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     }
     if constexpr (PREC) {
       // ---------------- W3b: t = A s^
-      if (!grid_barrier(a.bar, a.n_wg)) return;
+      if (!grid_barrier(gb)) return;
       mk.mark(15);
       if (wi.live && st.state == ST_ACTIVE && !half_done) {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
@@ -396,7 +397,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       }
     }
     // ---------------- W4
-    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (!grid_barrier(gb)) return;
     mk.mark(14);
     if (wi.live && st.state == ST_ACTIVE && !half_done) {
       const double2 ts = get_total(a, wi, SLOT_TS, sh);
@@ -437,11 +438,23 @@ __device__ inline void fields_to_lds(const SolveArgs& a, const WgInfo& wi, doubl
   __syncthreads();
 }
 
+// After a grid-barrier time-out: report the unfinished steps of the instance as failed launches.
+__device__ inline void fail_steps(const SolveArgs& a, const WgInfo& wi, int k) {
+  if (a.stats == nullptr || !wi.live || wi.g != 0 || threadIdx.x != 0) return;
+  for (int kk = k; kk < a.n_chunk; ++kk) {
+    StatsDev& o = a.stats[(size_t)kk * a.B + wi.b];
+    o.status = -2;  // TDDE_ERR_HIP
+    o.iters = o.matvecs = o.restarts = o.outer_iters = 0;
+    o.rel_res = o.true_rel_res = 0.0;
+  }
+}
+
 template <bool PREC, bool MIXED>
 __global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(PREC ? 2 : 4)))
 void persistent_kernel(SolveArgs a) {
   __shared__ Shared sh;
   Marks mk{a.marks, 0, a.n_marks};
+  GridBar gb{a.bar, (unsigned)a.n_wg, 0u, false};
   WgInfo wi;
   wi.G = a.G;
   wi.live = blockIdx.x < (unsigned)(a.B * a.G);
@@ -454,7 +467,7 @@ void persistent_kernel(SolveArgs a) {
   for (int k = 0; k < a.n_chunk; ++k) {
     const int step = a.step0 + k;
     int* cnt = a.counters + (size_t)k * kCounterPerStep;
-    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
     mk.mark(1);
     const bool inst = wi.live && (a.mode == MODE_SOLVE || a.n_steps == nullptr || step < a.n_steps[wi.b]);
     WgInfo wk = wi;
@@ -513,7 +526,7 @@ void persistent_kernel(SolveArgs a) {
     const bool need_r = MIXED || a.guess == GUESS_GIVEN || a.mode == MODE_SOLVE;
     if (need_r) {
       // r = b - A x0 in FP64 (the outer residual in mixed precision)
-      if (!grid_barrier(a.bar, a.n_wg)) return;
+      if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
       if (inst) {
         double2 rr = {0, 0};
         double2* rt = MIXED ? a.r64 + base : V.r + base;
@@ -535,7 +548,7 @@ void persistent_kernel(SolveArgs a) {
 
     if constexpr (!MIXED) {
       if (inst) counter_add(cnt, 1);
-      krylov<double, PREC>(a, wk, V, a.bvec, base, a.tol, a.max_iter, true, cnt, st, sh, mk);
+      krylov<double, PREC>(a, wk, V, a.bvec, base, a.tol, a.max_iter, true, cnt, st, sh, mk, gb);
     } else {
       // ---- FP64 iterative refinement around an FP32 BiCGSTAB (inner residuals, dots in FP64)
       KVec<float> U = a.v32;
@@ -545,7 +558,7 @@ void persistent_kernel(SolveArgs a) {
       int* ocnt = cnt + 1;
       if (inst) counter_add(ocnt, 1);
       for (int it = 0;; ++it) {
-        if (!grid_barrier(a.bar, a.n_wg)) return;
+        if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
         int* icnt = cnt + 2 + (it % (kCounterPerStep - 2));
         Inst ist = {};
         ist.state = ST_INACTIVE;
@@ -584,15 +597,15 @@ void persistent_kernel(SolveArgs a) {
             outer++;
           }
         }
-        if (!grid_barrier(a.bar, a.n_wg)) return;
+        if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
         if (__hip_atomic_load(ocnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
         WgInfo wq = wk;
         wq.live = ist.state == ST_ACTIVE;
-        krylov<float, PREC>(a, wq, U, a.rhs32, base, a.inner_tol, a.max_iter, false, icnt, ist, sh, mk);
+        krylov<float, PREC>(a, wq, U, a.rhs32, base, a.inner_tol, a.max_iter, false, icnt, ist, sh, mk, gb);
         total_iters += ist.iters;
         total_mv += ist.matvecs;
         // x += ||r|| d (FP64), then r = b - A x (FP64)
-        if (!grid_barrier(a.bar, a.n_wg)) return;
+        if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
         if (wq.live) {
           const float2* d = U.x + base;
           elem_own<double>(a, wk, [&](long e) {
@@ -600,7 +613,7 @@ void persistent_kernel(SolveArgs a) {
             x[e].y += rnorm * (double)d[e].y;
           });
         }
-        if (!grid_barrier(a.bar, a.n_wg)) return;
+        if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
         if (wq.live) {
           double2 rr = {0, 0};
           double2* rt = a.r64 + base;
@@ -620,7 +633,7 @@ void persistent_kernel(SolveArgs a) {
     }
 
     // ---- write back and statistics
-    if (!grid_barrier(a.bar, a.n_wg)) return;
+    if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
     mk.mark(2);
     if (inst) {
       double2* dst = a.mode == MODE_STEP ? a.psi + base : a.x_io + base;
@@ -637,7 +650,7 @@ void persistent_kernel(SolveArgs a) {
       }
     }
   }
-  grid_barrier(a.bar, a.n_wg);
+  grid_barrier(gb);
   mk.mark(3);
 }
 

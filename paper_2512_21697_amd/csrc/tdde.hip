@@ -403,7 +403,7 @@ tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
   c->n_wg = c->var_wg[0];
   c->G = c->n_wg / c->d.batch;
   if ((s = dev_alloc(c, &c->part, (size_t)max_wg * kSlots)) != TDDE_OK) return s;
-  if ((s = dev_alloc(c, &c->bar, 4)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->bar, kBarWords)) != TDDE_OK) return s;
   c->n_counters = 64 * kCounterPerStep;
   if ((s = dev_alloc(c, &c->counters, (size_t)c->n_counters)) != TDDE_OK) return s;
   c->stats_cap = c->d.batch;
@@ -654,7 +654,7 @@ static tdde_status run_persistent(tdde_ctx* c, SolveArgs& a, int n_chunk) {
   a.n_marks = c->n_marks;
   hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->counters),
                      c->n_counters);
-  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, c->stream, c->bar, 4);
+  hipLaunchKernelGGL(zero_words, dim3(8), dim3(256), 0, c->stream, c->bar, kBarWords);
   if (c->marks)
     hipLaunchKernelGGL(zero_words, dim3(16), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->marks),
                        2 * c->n_marks);
@@ -700,9 +700,9 @@ static tdde_status collect_stats(tdde_ctx* c, tdde_solve_stats* out) {
   std::vector<StatsDev> h(c->d.batch);
   HIP_TRY(c, hipMemcpyAsync(h.data(), c->stats_dev, h.size() * sizeof(StatsDev), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  unsigned barh[4] = {0, 0, 0, 0};
-  HIP_TRY(c, hipMemcpy(barh, c->bar, sizeof(barh), hipMemcpyDeviceToHost));
-  if (barh[2] != 0) return fail(c, TDDE_ERR_HIP, "grid barrier timed out (work-groups not co-resident)");
+  unsigned err_word = 0;
+  HIP_TRY(c, hipMemcpy(&err_word, c->bar + kBarErr, sizeof(err_word), hipMemcpyDeviceToHost));
+  if (err_word != 0) return fail(c, TDDE_ERR_HIP, "grid barrier timed out (work-groups not co-resident)");
   tdde_status worst = TDDE_OK;
   for (int b = 0; b < c->d.batch; ++b) {
     tdde_solve_stats& s = out[b];
