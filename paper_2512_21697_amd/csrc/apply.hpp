@@ -2,7 +2,8 @@
 //
 // eq. fullH: (H x)[j][s][i] = sum_{s',d} H0_j[s][s'][d][i] x[j][s'][i+d]
 //                           + sum_m coef_m f_m sum_{j'} (K^a A_m K^b)[j][j'] sum_{s',d} R_m[s][s'][d][i] x[j'][s'][i+d]
-// with H0_j = sum_n kappa_j^n h_n (+ per-channel complex band), S_j = sum_n kappa_j^n s_n or I.
+// with H0_j = sum_n kappa_j^n h_n (+ per-channel complex band), S_j = sum_n kappa_j^n s_n or I; the
+// kappa polynomials are summed once per distinct kappa on the host, so a tap is one band load.
 //
 // Work-group layout: 256 threads = 2 components x 128 radial points; thread (s, ii) owns
 // y[j][s][i0 + ii]. The x tile of channel j (with a halo of hb points) is staged in LDS; the
@@ -33,7 +34,9 @@ __device__ inline void stage_channel(c2_t<T> (*dst)[kHalo], const c2_t<T>* __res
 }
 
 // Stage w_k[s'][.] = sum_p val[p * K + k] * x[col[p]][s'][.] for the K terms of one pattern group and
-// the CSR row [p0, p1): every neighbouring x value is loaded once for all K terms.
+// the CSR row [p0, p1): every neighbouring x value is loaded once for all K terms. The neighbour
+// loads of kGatherBatch entries are issued together before they are used.
+constexpr int kGatherBatch = 4;
 template <typename T>
 __device__ inline void stage_gather(c2_t<T> (*dst)[2][kHalo], const c2_t<T>* __restrict__ xinst, const int* __restrict__ col,
                                     const T* __restrict__ val, int p0, int p1, int K, int i0, int nr) {
@@ -42,37 +45,82 @@ __device__ inline void stage_gather(c2_t<T> (*dst)[2][kHalo], const c2_t<T>* __r
   const size_t cstride = (size_t)2 * nr;
   for (int k = threadIdx.x; k < 2 * w; k += kThreads) {
     const int s = k / w, kk = k - s * w, gi = i0 - hb + kk;
+    const bool in = gi >= 0 && gi < nr;
+    const int gic = in ? gi : 0;
     c2_t<T> acc[kMaxGroup];
 #pragma unroll
     for (int q = 0; q < kMaxGroup; ++q) acc[q] = cmk<T>(0, 0);
-    if (gi >= 0 && gi < nr) {
-#pragma unroll 4
-      for (int p = p0; p < p1; ++p) {
-        const c2_t<T> xv = xinst[(size_t)col[p] * cstride + (size_t)s * nr + gi];
-        const T* v = val + (size_t)(p - p0) * K;
+    for (int pb = p0; pb < p1; pb += kGatherBatch) {
+      c2_t<T> xv[kGatherBatch];
 #pragma unroll
-        for (int q = 0; q < kMaxGroup; ++q)
-          if (q < K) acc[q] = rfma<T>(v[q], xv, acc[q]);
+      for (int u = 0; u < kGatherBatch; ++u) {
+        const int p = pb + u < p1 ? pb + u : p1 - 1;
+        xv[u] = xinst[(size_t)col[p] * cstride + (size_t)s * nr + gic];
+      }
+#pragma unroll
+      for (int u = 0; u < kGatherBatch; ++u) {
+        if (pb + u < p1) {
+          const T* v = val + (size_t)(pb + u - p0) * K;
+#pragma unroll
+          for (int q = 0; q < kMaxGroup; ++q)
+            if (q < K) acc[q] = rfma<T>(v[q], xv[u], acc[q]);
+        }
       }
     }
 #pragma unroll
     for (int q = 0; q < kMaxGroup; ++q)
-      if (q < K) dst[q][s][kk] = acc[q];
+      if (q < K) dst[q][s][kk] = in ? acc[q] : cmk<T>(0, 0);
   }
 }
 
 // Result of one tile apply for the calling thread: S x and H x at (j, s, i).
 template <typename T> struct SH { c2_t<T> sx, hx; };
 
+// Radial band taps of one (s, s') block at the calling thread's point: b[d] = B[s][s'][d][i].
+template <typename T> struct Taps { T v[2 * kHB + 1]; };
+template <typename T> struct CTaps { c2_t<T> v[2 * kHB + 1]; };
+
+template <typename T>
+__device__ inline void load_taps(Taps<T>& t, const T* p, int nr) {
+#pragma unroll
+  for (int d = 0; d < 2 * kHB + 1; ++d) t.v[d] = p[(size_t)d * nr];
+}
+template <typename T>
+__device__ inline void load_ctaps(CTaps<T>& t, const c2_t<T>* p, int nr) {
+#pragma unroll
+  for (int d = 0; d < 2 * kHB + 1; ++d) t.v[d] = p[(size_t)d * nr];
+}
+// acc += sum_d t[d] * x[ii + d] (x: staged LDS row with the halo)
+template <typename T>
+__device__ inline c2_t<T> contract(const Taps<T>& t, const c2_t<T>* x, c2_t<T> acc) {
+#pragma unroll
+  for (int d = 0; d < 2 * kHB + 1; ++d) acc = rfma<T>(t.v[d], x[d], acc);
+  return acc;
+}
+template <typename T>
+__device__ inline c2_t<T> ccontract(const CTaps<T>& t, const c2_t<T>* x, c2_t<T> acc) {
+#pragma unroll
+  for (int d = 0; d < 2 * kHB + 1; ++d) acc = cfma<T>(t.v[d], x[d], acc);
+  return acc;
+}
+
 // coef_f: LDS array [n_terms] of coef_m * f_{field_m}(t) for this instance.
+//
+// Latency structure: every global load of a phase is issued before its first use, and the
+// branches around loads depend only on the spinor component s, which is uniform over a wave
+// (128 threads per component), so they are scalar branches: H0/S taps are loaded before the
+// staging barrier is passed, coupling bands two terms at a time.
 template <typename T>
 __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict__ xinst, int j, int i0,
                                    const double2* coef_f, TileLds<T>& L) {
   constexpr int hb = kHB, nb = 2 * kHB + 1;
   const int nr = op.nr;
-  const int s = threadIdx.x / kTileR, ii = threadIdx.x - s * kTileR, i = i0 + ii;
+  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kTileR);
+  const int ii = threadIdx.x - s * kTileR, i = i0 + ii;
   const bool live = i < nr;
+  const int ic = live ? i : nr - 1;  // clamped point: loads stay in bounds, results unused
   const size_t cstride = (size_t)2 * nr;
+  const size_t bstride = (size_t)nb * nr;
   SH<T> out;
   out.sx = cmk<T>(0, 0);
   out.hx = cmk<T>(0, 0);
@@ -91,48 +139,62 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
       stage_gather<T>(L.ws, xinst, op.g_col, op.g_val + op.g_voff[0] + (size_t)(p0 - op.g_rowptr[0]) * K0, p0, p1, K0,
                       i0, nr);
   }
-  __syncthreads();
 
-  const T kap = op.kappa[j];
-  if (live) {
-    const size_t bstride = (size_t)nb * nr;
-    // H0 (kappa polynomial, Horner) and S; taps fully unrolled, polynomial coefficients loaded
-    // before the Horner chain so all loads of a tap are in flight together
-    const int n_h = op.n_h, n_s = op.n_s;
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const bool do_h = n_h > 0 && (op.pq_h || s2 == s);
-      const bool do_c = op.has_chan && (op.pq_chan || s2 == s);
-      const bool do_s = n_s > 0 && (op.pq_s || s2 == s);
-      if (!(do_h || do_c || do_s)) continue;
-      const size_t blk = (size_t)(s * 2 + s2) * bstride + i;
-      const T* hp = op.h_poly + blk;
-      const T* sp = op.s_poly + blk;
-      const c2_t<T>* hc = op.h_chan + (size_t)j * 4 * bstride + blk;
+  // ---- H0 / S / channel taps of this kappa block: the real tap blocks this thread needs are listed
+  // (uniform per wave; a complex channel block takes two, real and imaginary part), then loaded
+  // kTapRound at a time with all loads of a round issued before any is used.
+  constexpr int kTapSlots = 8, kTapRound = 4;
+  const int kb = op.kblk_of[j];
+  const T* sp[kTapSlots];
+  // per slot: x component, destination (0 = H, 1 = H times i, 2 = S), element stride (1 real, 2 complex part)
+  int sx2[kTapSlots], sdst[kTapSlots], sstr[kTapSlots];
+  int ns = 0;
+  auto add_slot = [&](const T* ptr, int s2, int dst, int str) {
 #pragma unroll
-      for (int d = -hb; d <= hb; ++d) {
-        const c2_t<T> xv = L.xs[s2][ii + hb + d];
-        const size_t off = (size_t)(d + hb) * nr;
-        if (do_h) {
-          T cf[4];
+    for (int k = 0; k < kTapSlots; ++k)
+      if (k == ns) { sp[k] = ptr; sx2[k] = s2; sdst[k] = dst; sstr[k] = str; }
+    ++ns;
+  };
 #pragma unroll
-          for (int n = 0; n < 4; ++n) cf[n] = n < n_h ? hp[(size_t)n * 4 * bstride + off] : (T)0;
-          const T tap = fma(fma(fma(cf[3], kap, cf[2]), kap, cf[1]), kap, cf[0]);
-          out.hx = rfma<T>(tap, xv, out.hx);
-        }
-        if (do_c) out.hx = cfma<T>(hc[off], xv, out.hx);
-        if (do_s) {
-          T cf[3];
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const size_t blk = ((size_t)kb * 4 + s * 2 + s2) * bstride + ic;
+    if (op.n_h > 0 && (op.pq_h || s2 == s)) add_slot(op.h_blk + blk, s2, 0, 1);
+    if (op.n_s > 0 && (op.pq_s || s2 == s)) add_slot(op.s_blk + blk, s2, 2, 1);
+    if (op.has_chan && (op.pq_chan || s2 == s)) {
+      const T* cp = reinterpret_cast<const T*>(op.h_chan + ((size_t)j * 4 + s * 2 + s2) * bstride + ic);
+      add_slot(cp, s2, 0, 2);
+      add_slot(cp + 1, s2, 1, 2);
+    }
+  }
 #pragma unroll
-          for (int n = 0; n < 3; ++n) cf[n] = n < n_s ? sp[(size_t)n * 4 * bstride + off] : (T)0;
-          const T tap = fma(fma(cf[2], kap, cf[1]), kap, cf[0]);
-          out.sx = rfma<T>(tap, xv, out.sx);
-        }
+  for (int r = 0; r < kTapSlots / kTapRound; ++r) {
+    Taps<T> tt[kTapRound];
+#pragma unroll
+    for (int k = 0; k < kTapRound; ++k) {
+      const int sl = r * kTapRound + k;
+      if (sl < ns) {
+        const T* p = sp[sl];
+        const size_t dstep = (size_t)nr * sstr[sl];
+#pragma unroll
+        for (int d = 0; d < nb; ++d) tt[k].v[d] = p[d * dstep];
       }
     }
-    if (op.n_s == 0) out.sx = L.xs[s][ii + hb];
+    if (r == 0) __syncthreads();  // staged x visible (the first round's loads are already in flight)
+#pragma unroll
+    for (int k = 0; k < kTapRound; ++k) {
+      const int sl = r * kTapRound + k;
+      if (sl < ns) {
+        const c2_t<T> a = contract<T>(tt[k], &L.xs[sx2[sl]][ii], cmk<T>(0, 0));
+        if (sdst[sl] == 2) out.sx = cadd<T>(out.sx, a);
+        else if (sdst[sl] == 1) out.hx = cadd<T>(out.hx, cmk<T>(-a.y, a.x));
+        else out.hx = cadd<T>(out.hx, a);
+      }
+    }
   }
+  if (op.n_s == 0) out.sx = L.xs[s][ii + hb];
 
-  // coupling terms: stage the angular combinations of a pattern group, then the band contractions
+  // ---- coupling terms: stage the angular combinations of a pattern group, then the band
+  // contractions, the bands of two terms loaded together
   for (int gidx = 0; gidx < op.n_groups; ++gidx) {
     const int f0 = op.g_first[gidx], K = op.g_first[gidx + 1] - f0;
     const int* rp = op.g_rowptr + (size_t)gidx * (op.nang + 1);
@@ -149,22 +211,32 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
       stage_gather<T>(L.ws, xinst, op.g_col, op.g_val + op.g_voff[gidx] + (size_t)(p0 - rp[0]) * K, p0, p1, K, i0, nr);
       __syncthreads();
     }
-    if (live) {
-      const size_t bstride = (size_t)nb * nr;
-      for (int q = 0; q < K; ++q) {
-        const int m = op.g_term[f0 + q];
-        const double2 cf = coef_f[m];
-        if (cf.x == 0.0 && cf.y == 0.0) continue;
-        const T* R = op.t_r + (size_t)m * 4 * bstride;
-        const bool pq = op.t_pq[m] != 0;
-        c2_t<T> acc = cmk<T>(0, 0);
-        for (int s2 = 0; s2 < 2; ++s2) {
-          if (!pq && s2 != s) continue;
-          const T* Rb = R + (size_t)(s * 2 + s2) * bstride + i;
 #pragma unroll
-          for (int d = -hb; d <= hb; ++d) acc = rfma<T>(Rb[(size_t)(d + hb) * nr], L.ws[q][s2][ii + hb + d], acc);
+    for (int q0 = 0; q0 < kMaxGroup; q0 += 2) {
+      if (q0 < K) {
+        Taps<T> tr[2][2];
+        int mask[2], m[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int q = q0 + h;
+          m[h] = q < K ? op.g_term[f0 + q] : 0;
+          mask[h] = q < K ? __builtin_amdgcn_readfirstlane((op.t_mask[m[h]] >> (2 * s)) & 3) : 0;
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2)
+            if ((mask[h] >> s2) & 1)
+              load_taps<T>(tr[h][s2], op.t_r + ((size_t)m[h] * 4 + s * 2 + s2) * bstride + ic, nr);
         }
-        out.hx = cfma<T>(cmk<T>((T)cf.x, (T)cf.y), acc, out.hx);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (q0 + h < K) {
+            c2_t<T> acc = cmk<T>(0, 0);
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2)
+              if ((mask[h] >> s2) & 1) acc = contract<T>(tr[h][s2], &L.ws[q0 + h][s2][ii], acc);
+            const double2 cf = coef_f[m[h]];
+            out.hx = cfma<T>(cmk<T>((T)cf.x, (T)cf.y), acc, out.hx);
+          }
+        }
       }
     }
   }

@@ -55,10 +55,12 @@ template <typename T> struct DevOp {
   int pq_h, pq_s, pq_chan;     // 1 when the blocks couple s != s'
   int n_terms;
   int n_itiles;                // ceil(nr / kTileR)
-  const T* kappa;              // [nang]
-  const T* h_poly;             // [n_h][2][2][nb][nr]
+  // H0 and S of every distinct kappa, the kappa polynomials summed on the host:
+  // h_blk[kb][s][s'][d][i] = sum_n kappa^n h_n[s][s'][d][i] (likewise s_blk), kb = kblk_of[j]
+  const int* kblk_of;          // [nang]
+  const T* h_blk;              // [n_kblk][2][2][nb][nr] (null when n_h == 0)
   const c2_t<T>* h_chan;       // [nang][2][2][nb][nr]
-  const T* s_poly;             // [n_s][2][2][nb][nr]
+  const T* s_blk;              // [n_kblk][2][2][nb][nr] (null when n_s == 0: S = I)
   // Terms with one angular sparsity pattern form a group and are staged together:
   // group g holds terms g_term[g_first[g] .. g_first[g+1]); its pattern is g_rowptr[g][nang+1]
   // (absolute offsets into g_col); the value of term k of the group at pattern entry p is
@@ -72,7 +74,7 @@ template <typename T> struct DevOp {
   const long* g_voff;          // [n_groups]
   const T* g_val;
   const T* t_r;                // [n_terms][2][2][nb][nr]
-  const int* t_pq;             // [n_terms]
+  const int* t_mask;           // [n_terms] bit (2 s + s') set when block (s, s') of R_m is nonzero
   const int* t_field;          // [n_terms]
   const double2* t_coef;       // [n_terms] (double even for the FP32 copy)
 };

@@ -49,74 +49,149 @@ template <typename T> struct ChainIO {
   const c2_t<T>* v;   // v (channel base)
   c2_t<T>* out;       // preconditioned result (channel base)
   double2 c1, c2;     // MODE_P: (beta, omega); MODE_S: (alpha, -)
-  int mode;
 };
 
-template <typename T>
-__device__ inline c2_t<T> chain_input(const ChainIO<T>& io, size_t e, bool store) {
-  c2_t<T> z;
-  if (io.mode == MODE_P) {
-    const c2_t<T> omega = cmk<T>((T)io.c2.x, (T)io.c2.y), beta = cmk<T>((T)io.c1.x, (T)io.c1.y);
-    const c2_t<T> pv = csub<T>(io.pz[e], cmul<T>(omega, io.v[e]));
-    z = cfma<T>(beta, pv, io.r[e]);
-  } else if (io.mode == MODE_S) {
-    z = csub<T>(io.r[e], cmul<T>(cmk<T>((T)io.c1.x, (T)io.c1.y), io.v[e]));
-  } else if (io.mode == MODE_FRESH) {
-    z = io.r[e];
+// Rows a lane keeps in flight during a substitution: the operands of the next kChainAhead rows are
+// loaded before the current row is computed and its results stored, so the loads overlap the
+// arithmetic of the rows before them instead of one memory latency being paid per row.
+#ifndef TDDE_CHAIN_AHEAD
+#define TDDE_CHAIN_AHEAD 2
+#endif
+constexpr int kChainAhead = TDDE_CHAIN_AHEAD;
+
+// Substitution kinds: lower phase 1 (forms the input), lower phase 3, upper phase 1, upper phase 3.
+enum { SUB_L1 = 0, SUB_L3 = 1, SUB_U1 = 2, SUB_U3 = 3 };
+
+// Operands of one row: the factor entries (L row: W values; U row: 1/U(q,q) and W values) and the
+// raw vector values the right-hand side is formed from.
+template <typename T, int NC> struct RowOps {
+  c2_t<T> c[NC];
+  c2_t<T> z0, z1, z2;
+};
+
+template <typename T, int KIND, int MODE, int NC>
+__device__ inline void row_fetch(RowOps<T, NC>& ro, const c2_t<T>* LU, const ChainIO<T>& io, int nr, int q) {
+  const size_t e = prow(q, nr);
+  const c2_t<T>* row = LU + (size_t)q * kPrecStride + (KIND <= SUB_L3 ? 0 : kPrecW);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) ro.c[k] = row[k];
+  if (KIND == SUB_L1) {
+    if constexpr (MODE == MODE_P) { ro.z0 = io.r[e]; ro.z1 = io.pz[e]; ro.z2 = io.v[e]; }
+    else if constexpr (MODE == MODE_S) { ro.z0 = io.r[e]; ro.z2 = io.v[e]; }
+    else if constexpr (MODE == MODE_FRESH) { ro.z0 = io.r[e]; }
+    else { ro.z0 = io.pz[e]; }
+  } else if (KIND == SUB_L3) {
+    ro.z0 = io.pz[e];  // the input formed (and stored) in phase 1
   } else {
-    z = io.pz[e];
+    ro.z0 = io.out[e];  // y of the lower solve (U1), or y overwritten by nothing yet (U3)
   }
-  if (store && io.mode != MODE_IN && io.mode != MODE_IN_S) io.pz[e] = z;
-  return z;
 }
 
-// One lane: forward substitution over rows [o, o+len) from the window win (win[k] = y_{o-1-k}).
-// phase 1: forms the input (stores it, accumulates |z|^2), keeps the window only.
-// phase 3: reads the stored input, writes y into io.out.
-template <typename T, int W>
-__device__ inline void lower_segment(const c2_t<T>* __restrict__ LU, const ChainIO<T>& io, int nr, int o, int len,
-                                     c2_t<T> (&win)[W], bool phase1, double& nrm2) {
-  for (int q = o; q < o + len; ++q) {
-    const size_t e = prow(q, nr);
-    c2_t<T> acc;
-    if (phase1) {
-      acc = chain_input<T>(io, e, true);
-      nrm2 += (double)acc.x * acc.x + (double)acc.y * acc.y;
-    } else {
-      acc = io.pz[e];  // the input formed (and stored) in phase 1
+// Right-hand side value of a lower phase-1 row from its raw operands:
+//   MODE_P:  z = r + beta (p - omega v)   (BiCGSTAB direction update; z is stored into p)
+//   MODE_S:  z = r - alpha v              (BiCGSTAB half step;        z is stored into s)
+//   MODE_FRESH: z = r (stored into p); MODE_IN, MODE_IN_S: z = input (not rewritten)
+template <typename T, int MODE, int NC>
+__device__ inline c2_t<T> row_input(const RowOps<T, NC>& ro, const ChainIO<T>& io) {
+  if constexpr (MODE == MODE_P) {
+    const c2_t<T> omega = cmk<T>((T)io.c2.x, (T)io.c2.y), beta = cmk<T>((T)io.c1.x, (T)io.c1.y);
+    return cfma<T>(beta, csub<T>(ro.z1, cmul<T>(omega, ro.z2)), ro.z0);
+  } else if constexpr (MODE == MODE_S) {
+    return csub<T>(ro.z0, cmul<T>(cmk<T>((T)io.c1.x, (T)io.c1.y), ro.z2));
+  } else {
+    return ro.z0;
+  }
+}
+
+// One lane's substitution through its segment [o, o+len) from the window win.
+//   lower (L1, L3): rows ascending, win[k] = y_{q-1-k}; y_q = z_q - sum_k L(q, q-1-k) win[k]
+//   upper (U1, U3): rows descending, win[k] = x_{q+1+k}; x_q = (y_q - sum_k U(q, q+1+k) win[k]) / U(q,q)
+// Phase 1 kinds keep only the window (L1 also stores the formed input and accumulates |z|^2);
+// phase 3 kinds write the result into io.out.
+template <typename T, int KIND, int MODE, int W>
+__device__ inline void substitute(const c2_t<T>* LU, const ChainIO<T>& io, int nr, int o, int len, c2_t<T> (&win)[W],
+                                  double& nrm2) {
+  constexpr bool lower = KIND <= SUB_L3;
+  constexpr int NC = lower ? W : W + 1;
+  constexpr int D = kChainAhead;
+  RowOps<T, NC> ro[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (d < len) row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, lower ? o + d : o + len - 1 - d);
+  for (int t0 = 0; t0 < len; t0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int t = t0 + d;
+      if (t < len) {
+        const int q = lower ? o + t : o + len - 1 - t;
+        const size_t e = prow(q, nr);
+        c2_t<T> acc;
+        if (KIND == SUB_L1) {
+          acc = row_input<T, MODE, NC>(ro[d], io);
+          nrm2 += (double)acc.x * acc.x + (double)acc.y * acc.y;
+        } else {
+          acc = ro[d].z0;
+        }
+        const c2_t<T> zin = acc;
+#pragma unroll
+        for (int k = 0; k < W; ++k) acc = csub<T>(acc, cmul<T>(ro[d].c[lower ? k : k + 1], win[k]));
+        if (!lower) acc = cmul<T>(acc, ro[d].c[0]);
+#pragma unroll
+        for (int k = W - 1; k > 0; --k) win[k] = win[k - 1];
+        win[0] = acc;
+        // loads of row t + D are issued before this row's stores, so waiting for them later does
+        // not wait for the stores
+        if (t + D < len) row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, lower ? o + t + D : o + len - 1 - t - D);
+        if (KIND == SUB_L1 && MODE != MODE_IN && MODE != MODE_IN_S) io.pz[e] = zin;
+        if (KIND == SUB_L3 || KIND == SUB_U3) io.out[e] = acc;
+      }
     }
-    const c2_t<T>* row = LU + (size_t)q * kPrecStride;
-#pragma unroll
-    for (int k = 0; k < W; ++k) acc = csub<T>(acc, cmul<T>(row[k], win[k]));
-#pragma unroll
-    for (int k = W - 1; k > 0; --k) win[k] = win[k - 1];
-    win[0] = acc;
-    if (!phase1) io.out[e] = acc;
   }
 }
 
-// One lane: backward substitution over rows [o, o+len) (q descending) from the window
-// win (win[k] = x_{o+len+k}). Reads y from io.out; phase 3 overwrites it with x.
-template <typename T, int W>
-__device__ inline void upper_segment(const c2_t<T>* __restrict__ LU, const ChainIO<T>& io, int nr, int o, int len,
-                                     c2_t<T> (&win)[W], bool phase1) {
-  for (int q = o + len - 1; q >= o; --q) {
-    const size_t e = prow(q, nr);
-    c2_t<T> acc = io.out[e];
-    const c2_t<T>* row = LU + (size_t)q * kPrecStride;
+// Ordering of LDS accesses between lanes of one wave: a wave executes its LDS operations in issue
+// order, so only the compiler has to be kept from moving them across this point.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Boundary propagation over the segments: lane r < W owns row r of the w x w coupling matrices and
+// of the windows; the T row of the next step is loaded one step ahead.
+//   lower: t_p = g_p - T_p t_{p-1}, p = 1 .. P-1; upper: h_p = g_p - T_p h_{p+1}, p = P-2 .. 0.
+template <typename T, bool LOWER, int W>
+__device__ inline void propagate(const c2_t<T>* Tm, int P, c2_t<T>* lds) {
+  const int lane = threadIdx.x & 63;
+  const int first = LOWER ? 1 : P - 2, count = P - 1;
+  c2_t<T> tr[W];
+  if (lane < W && count > 0) {
 #pragma unroll
-    for (int k = 0; k < W; ++k) acc = csub<T>(acc, cmul<T>(row[W + 1 + k], win[k]));
-    acc = cmul<T>(acc, row[W]);
+    for (int c = 0; c < W; ++c) tr[c] = Tm[((size_t)first * W + lane) * W + c];
+  }
+  for (int k = 0; k < count; ++k) {
+    const int p = LOWER ? first + k : first - k;
+    const int prev = LOWER ? p - 1 : p + 1;
+    c2_t<T> acc = cmk<T>(0, 0);
+    if (lane < W) {
+      acc = lds[p * W + lane];
 #pragma unroll
-    for (int k = W - 1; k > 0; --k) win[k] = win[k - 1];
-    win[0] = acc;
-    if (!phase1) io.out[e] = acc;
+      for (int c = 0; c < W; ++c) acc = csub<T>(acc, cmul<T>(tr[c], lds[prev * W + c]));
+      if (k + 1 < count) {
+        const int pn = LOWER ? p + 1 : p - 1;
+#pragma unroll
+        for (int c = 0; c < W; ++c) tr[c] = Tm[((size_t)pn * W + lane) * W + c];
+      }
+    }
+    wave_sync();
+    if (lane < W) lds[p * W + lane] = acc;
+    wave_sync();
   }
 }
 
 // Solve M_blk z = input for one channel with one wave (the calling wave; lanes = segments).
 // lds: kMaxSeg * W complex values. Returns the |input|^2 sum of the chain (valid in lane 0).
-template <typename T>
+template <typename T, int MODE>
 __device__ inline double chain_solve(const DevPrec<T>& pc, int blk, int nr, const ChainIO<T>& io, c2_t<T>* lds) {
   constexpr int W = kPrecW;
   const int lane = threadIdx.x & 63;
@@ -126,86 +201,44 @@ __device__ inline double chain_solve(const DevPrec<T>& pc, int blk, int nr, cons
   const c2_t<T>* TU = pc.TU + (size_t)blk * P * W * W;
   const int o = lane * m;
   const int len = lane < P ? min(m, n - o) : 0;
-  double nrm2 = 0.0;
+  double nrm2 = 0.0, dummy = 0.0;
   c2_t<T> win[W];
 
-  // ---- lower solve, phase 1: local windows
+  // ---- lower solve, phase 1: local windows; tail t_p[c] = y[o + len - W + c] = win[W-1-c]
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  if (len > 0) lower_segment<T, W>(LU, io, nr, o, len, win, true, nrm2);
-  // tail t_p[c] = y[o + len - W + c] = win[W-1-c]
+  substitute<T, SUB_L1, MODE, W>(LU, io, nr, o, len, win, nrm2);
   if (lane < P) {
 #pragma unroll
     for (int c = 0; c < W; ++c) lds[lane * W + c] = win[W - 1 - c];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  // ---- phase 2: t_p = g_p - T_p t_{p-1}, sequential over p, lanes 0..W-1 own rows of T_p
-  for (int p = 1; p < P; ++p) {
-    c2_t<T> acc = cmk<T>(0, 0);
-    if (lane < W) {
-      acc = lds[p * W + lane];
-      const c2_t<T>* Tp = TL + ((size_t)p * W + lane) * W;
-#pragma unroll
-      for (int c = 0; c < W; ++c) acc = csub<T>(acc, cmul<T>(Tp[c], lds[(p - 1) * W + c]));
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    if (lane < W) lds[p * W + lane] = acc;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  }
+  wave_sync();
+  // ---- phase 2: true tails
+  propagate<T, true, W>(TL, P, lds);
   // ---- phase 3: final substitution from the true window win[k] = y_{o-1-k} = t_{p-1}[W-1-k]
-  if (len > 0) {
 #pragma unroll
-    for (int k = 0; k < W; ++k) win[k] = lane > 0 ? lds[(lane - 1) * W + (W - 1 - k)] : cmk<T>(0, 0);
-    double dummy = 0.0;
-    lower_segment<T, W>(LU, io, nr, o, len, win, false, dummy);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int k = 0; k < W; ++k) win[k] = (lane > 0 && lane < P) ? lds[(lane - 1) * W + (W - 1 - k)] : cmk<T>(0, 0);
+  wave_sync();
+  substitute<T, SUB_L3, MODE, W>(LU, io, nr, o, len, win, dummy);
 
   // ---- upper solve, phase 1: heads h_p[c] = x[o + c] = win[c] with zero incoming window
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  if (len > 0) upper_segment<T, W>(LU, io, nr, o, len, win, true);
+  substitute<T, SUB_U1, MODE, W>(LU, io, nr, o, len, win, dummy);
   if (lane < P) {
 #pragma unroll
     for (int c = 0; c < W; ++c) lds[lane * W + c] = win[c];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  wave_sync();
   // ---- phase 2: h_p = g_p - TU_p h_{p+1}, p descending
-  for (int p = P - 2; p >= 0; --p) {
-    c2_t<T> acc = cmk<T>(0, 0);
-    if (lane < W) {
-      acc = lds[p * W + lane];
-      const c2_t<T>* Tp = TU + ((size_t)p * W + lane) * W;
-#pragma unroll
-      for (int c = 0; c < W; ++c) acc = csub<T>(acc, cmul<T>(Tp[c], lds[(p + 1) * W + c]));
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    if (lane < W) lds[p * W + lane] = acc;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  }
+  propagate<T, false, W>(TU, P, lds);
   // ---- phase 3: x from the true incoming window win[k] = x_{o+len+k} = h_{p+1}[k]
-  if (len > 0) {
 #pragma unroll
-    for (int k = 0; k < W; ++k) win[k] = lane + 1 < P ? lds[(lane + 1) * W + k] : cmk<T>(0, 0);
-    upper_segment<T, W>(LU, io, nr, o, len, win, false);
-  }
+  for (int k = 0; k < W; ++k) win[k] = lane + 1 < P ? lds[(lane + 1) * W + k] : cmk<T>(0, 0);
+  wave_sync();
+  substitute<T, SUB_U3, MODE, W>(LU, io, nr, o, len, win, dummy);
   // |input|^2 of the chain
   for (int off = 32; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off, 64);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   return nrm2;
 }
 

@@ -180,10 +180,10 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
 }
 __device__ inline double2 dmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
-// Preconditioner chain phase for own channels: mode MODE_P / MODE_FRESH / MODE_S.
-template <typename T>
-__device__ inline double chains_own(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, size_t base, int mode,
-                                    double2 c1, double2 c2, Shared& sh) {
+// Preconditioner chain phase for own channels (MODE_P / MODE_FRESH / MODE_IN_S).
+template <typename T, int MODE>
+__device__ inline double chains_own(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, size_t base, double2 c1,
+                                    double2 c2, Shared& sh) {
   const DevOp<T>& op = op_of<T>(a);
   const DevPrec<T>& pc = pc_of<T>(a);
   double nrm2 = 0.0;
@@ -193,13 +193,12 @@ __device__ inline double chains_own(const SolveArgs& a, const WgInfo& wi, const 
       ChainIO<T> io;
       io.r = V.r + cb;
       io.v = V.v + cb;
-      const bool on_s = mode == MODE_S || mode == MODE_IN_S;
+      constexpr bool on_s = MODE == MODE_S || MODE == MODE_IN_S;
       io.pz = (on_s ? V.s : V.p) + cb;
       io.out = (on_s ? V.sh : V.ph) + cb;
       io.c1 = c1;
       io.c2 = c2;
-      io.mode = mode;
-      const double n2 = chain_solve<T>(pc, pc.block_of[j_], op.nr, io, lds_of<T>(sh).chain);
+      const double n2 = chain_solve<T, MODE>(pc, pc.block_of[j_], op.nr, io, lds_of<T>(sh).chain);
       if (threadIdx.x == 0) nrm2 += n2;
     }
   }
@@ -276,7 +275,8 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     }
     if (work) {
       if constexpr (PREC) {
-        chains_own<T>(a, wi, V, base, st.fresh ? MODE_FRESH : MODE_P, beta, st.omega, sh);
+        if (st.fresh) chains_own<T, MODE_FRESH>(a, wi, V, base, beta, st.omega, sh);
+        else chains_own<T, MODE_P>(a, wi, V, base, beta, st.omega, sh);
       } else {
         const c2_t<T> bc = to_c<T>(beta), oc = to_c<T>(st.omega);
         const bool fr = st.fresh;
@@ -365,7 +365,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         if (!verify) { st.true_rel_res = st.rel_res; counter_add(cnt, -1); }
         half_done = true;
       } else if constexpr (PREC) {
-        chains_own<T>(a, wi, V, base, MODE_IN_S, st.alpha, st.alpha, sh);  // s^ = K^-1 s
+        chains_own<T, MODE_IN_S>(a, wi, V, base, st.alpha, st.alpha, sh);  // s^ = K^-1 s
       } else {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
         apply_own<T>(a, wi, s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
@@ -450,7 +450,7 @@ __device__ inline void fail_steps(const SolveArgs& a, const WgInfo& wi, int k) {
 }
 
 template <bool PREC, bool MIXED>
-__global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(PREC ? 2 : 4)))
+__global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(PREC ? 1 : 2)))
 void persistent_kernel(SolveArgs a) {
   __shared__ Shared sh;
   Marks mk{a.marks, 0, a.n_marks};

@@ -157,8 +157,7 @@ __global__ __launch_bounds__(64) void precond_kernel(DevPrec<T> pc, int nr, cons
   io.pz = const_cast<c2_t<T>*>(in) + cb;
   io.out = out + cb;
   io.c1 = io.c2 = make_double2(0, 0);
-  io.mode = MODE_IN;
-  chain_solve<T>(pc, pc.block_of[j], nr, io, lds);
+  chain_solve<T, MODE_IN>(pc, pc.block_of[j], nr, io, lds);
 }
 
 // ------------------------------------------------------------------------------------------ helpers
@@ -223,7 +222,7 @@ tdde_status tdde_destroy(tdde_ctx* ctx) {
 
 template <typename T>
 static tdde_status build_devop(tdde_ctx* c, const tdde_operator_desc* o, DevOp<T>& op, const std::vector<double>& tval,
-                               const std::vector<int>& rowptr_abs, const std::vector<int>& pq) {
+                               const std::vector<int>& rowptr_abs, const std::vector<int>& mask) {
   const int nr = c->d.nr, nang = c->d.nang, hb = c->d.half_band, nb = 2 * hb + 1;
   const size_t bsz = (size_t)4 * nb * nr;
   op.nr = nr; op.nang = nang; op.hb = hb; op.nb = nb;
@@ -244,10 +243,45 @@ static tdde_status build_devop(tdde_ctx* c, const tdde_operator_desc* o, DevOp<T
     }
   };
   tdde_status s;
-  std::vector<double> kap(o->kappa, o->kappa + nang);
-  if ((s = up((T**)&op.kappa, kap.data(), nang)) != TDDE_OK) return s;
-  if ((s = up((T**)&op.h_poly, o->n_h ? o->h_poly : nullptr, (size_t)o->n_h * bsz)) != TDDE_OK) return s;
-  if ((s = up((T**)&op.s_poly, o->n_s ? o->s_poly : nullptr, (size_t)o->n_s * bsz)) != TDDE_OK) return s;
+  // H0 and S per distinct kappa: the kappa polynomials summed (Horner) on the host
+  {
+    std::map<double, int> seen;
+    std::vector<int> kblk(nang);
+    std::vector<double> kvals;
+    for (int j = 0; j < nang; ++j) {
+      auto it = seen.find(o->kappa[j]);
+      if (it == seen.end()) {
+        it = seen.emplace(o->kappa[j], (int)kvals.size()).first;
+        kvals.push_back(o->kappa[j]);
+      }
+      kblk[j] = it->second;
+    }
+    const int nkb = (int)kvals.size();
+    auto sum_poly = [&](const double* poly, int npoly, std::vector<double>& outv) {
+      outv.assign((size_t)nkb * bsz, 0.0);
+      for (int kb = 0; kb < nkb; ++kb) {
+        const double kap = kvals[kb];
+        double* dst = outv.data() + (size_t)kb * bsz;
+        for (size_t e = 0; e < bsz; ++e) {
+          double acc = poly[(size_t)(npoly - 1) * bsz + e];
+          for (int n = npoly - 2; n >= 0; --n) acc = std::fma(acc, kap, poly[(size_t)n * bsz + e]);
+          dst[e] = acc;
+        }
+      }
+    };
+    if ((s = upload(c, (int**)&op.kblk_of, kblk.data(), kblk.size())) != TDDE_OK) return s;
+    std::vector<double> blk;
+    op.h_blk = nullptr;
+    op.s_blk = nullptr;
+    if (o->n_h > 0) {
+      sum_poly(o->h_poly, o->n_h, blk);
+      if ((s = up((T**)&op.h_blk, blk.data(), blk.size())) != TDDE_OK) return s;
+    }
+    if (o->n_s > 0) {
+      sum_poly(o->s_poly, o->n_s, blk);
+      if ((s = up((T**)&op.s_blk, blk.data(), blk.size())) != TDDE_OK) return s;
+    }
+  }
   if (op.has_chan) {
     if ((s = up((T**)&op.h_chan, o->h_chan, (size_t)nang * bsz * 2)) != TDDE_OK) return s;
   } else {
@@ -296,7 +330,7 @@ static tdde_status build_devop(tdde_ctx* c, const tdde_operator_desc* o, DevOp<T
     if ((s = up((T**)&op.g_val, g_val.data(), g_val.size())) != TDDE_OK) return s;
   }
   if ((s = up((T**)&op.t_r, o->n_terms ? o->r_band : nullptr, (size_t)o->n_terms * bsz)) != TDDE_OK) return s;
-  if ((s = upload(c, (int**)&op.t_pq, pq.data(), pq.size())) != TDDE_OK) return s;
+  if ((s = upload(c, (int**)&op.t_mask, mask.data(), mask.size())) != TDDE_OK) return s;
   if ((s = upload(c, (int**)&op.t_field, o->field, (size_t)o->n_terms)) != TDDE_OK) return s;
   if ((s = upload(c, (double2**)&op.t_coef, (const double2*)o->coef, (size_t)o->n_terms)) != TDDE_OK) return s;
   return TDDE_OK;
@@ -327,7 +361,7 @@ tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
   // validate CSR and fold kappa exponents into the values
   std::vector<int> rowptr_abs((size_t)o->n_terms * (nang + 1));
   std::vector<double> tval;
-  std::vector<int> pq(o->n_terms);
+  std::vector<int> mask(o->n_terms);
   const int64_t nnz = o->n_terms ? o->a_off[o->n_terms] : 0;
   if (nnz > INT32_MAX) return fail(c, TDDE_ERR_ARG, "too many coupling nonzeros");
   tval.resize(nnz);
@@ -350,11 +384,16 @@ tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
         if (jj < 0 || jj >= nang) return fail(c, TDDE_ERR_ARG, "column index out of range");
         tval[off + p] = std::pow(o->kappa[j], ka) * o->a_val[off + p] * std::pow(o->kappa[jj], kb);
       }
-    pq[m] = any_offdiag(o->r_band + (size_t)m * 4 * nb * nr, 1, hb, nr, 1) ? 1 : 0;
+    mask[m] = 0;
+    for (int sel = 0; sel < 4; ++sel) {
+      const double* rb = o->r_band + ((size_t)m * 4 + sel) * nb * nr;
+      for (size_t k = 0; k < (size_t)nb * nr; ++k)
+        if (rb[k] != 0.0) { mask[m] |= 1 << sel; break; }
+    }
   }
   tdde_status s;
-  if ((s = build_devop<double>(c, o, c->op64, tval, rowptr_abs, pq)) != TDDE_OK) return s;
-  if ((s = build_devop<float>(c, o, c->op32, tval, rowptr_abs, pq)) != TDDE_OK) return s;
+  if ((s = build_devop<double>(c, o, c->op64, tval, rowptr_abs, mask)) != TDDE_OK) return s;
+  if ((s = build_devop<float>(c, o, c->op32, tval, rowptr_abs, mask)) != TDDE_OK) return s;
   // host copies for the preconditioner
   const size_t bsz = (size_t)4 * nb * nr;
   c->kappa.assign(o->kappa, o->kappa + nang);
