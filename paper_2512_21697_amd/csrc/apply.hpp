@@ -15,10 +15,51 @@
 
 namespace tdde {
 
+constexpr int kGatherMax = 64;  // CSR entries of one pattern row staged in LDS at a time
+
 template <typename T> struct TileLds {
   c2_t<T> xs[2][kHalo];
   c2_t<T> ws[kMaxGroup][2][kHalo];
+  int gcol[kGatherMax];
+  T gval[kGatherMax * kMaxGroup];
 };
+
+// Coupling-term table of one instance at one time, in LDS: coef_f[m] = coef_m * f_{field_m}(t);
+// per group slot the term index and its nonzero-block mask; g_live[g] when any coefficient of
+// group g is nonzero.
+struct TermLds {
+  double2 coef_f[kMaxTerms];
+  int g_first[kMaxTerms + 1];
+  int g_term[kMaxTerms];
+  int g_mask[kMaxTerms];
+  int g_live[kMaxTerms];
+};
+
+// Fill the term table (all threads call; ends with a barrier). fval(m) = f_{field_m}(t).
+template <typename T, typename F>
+__device__ inline void terms_to_lds(const DevOp<T>& op, TermLds& tl, F&& fval) {
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < op.n_terms) {
+    const double f = fval(t);
+    const double2 c = op.t_coef[t];
+    tl.coef_f[t] = make_double2(c.x * f, c.y * f);
+    const int m = op.g_term[t];
+    tl.g_term[t] = m;
+    tl.g_mask[t] = op.t_mask[m];
+  }
+  if (t <= op.n_groups) tl.g_first[t] = op.g_first[t];
+  __syncthreads();
+  if (t < op.n_groups) {
+    bool any = false;
+    for (int q = tl.g_first[t]; q < tl.g_first[t + 1]; ++q) {
+      const double2 cf = tl.coef_f[tl.g_term[q]];
+      any = any || cf.x != 0.0 || cf.y != 0.0;
+    }
+    tl.g_live[t] = any ? 1 : 0;
+  }
+  __syncthreads();
+}
 
 // Stage v[s'][i0-hb .. i0+kTileR+hb) of one channel into dst (zero outside [0, nr)).
 template <typename T>
@@ -33,16 +74,30 @@ __device__ inline void stage_channel(c2_t<T> (*dst)[kHalo], const c2_t<T>* __res
   }
 }
 
+// CSR row [p0, p1) of one pattern group (column indices and the K term values of every entry)
+// into LDS; at most kGatherMax entries (rows with more take the direct path of stage_gather).
+template <typename T>
+__device__ inline void stage_csr(TileLds<T>& L, const int* __restrict__ col, const T* __restrict__ val, int p0, int p1,
+                                 int K) {
+  const int n = p1 - p0;
+  if (n > kGatherMax) return;
+  for (int k = threadIdx.x; k < n; k += kThreads) L.gcol[k] = col[p0 + k];
+  for (int k = threadIdx.x; k < n * K; k += kThreads) L.gval[k] = val[k];
+}
+
 // Stage w_k[s'][.] = sum_p val[p * K + k] * x[col[p]][s'][.] for the K terms of one pattern group and
-// the CSR row [p0, p1): every neighbouring x value is loaded once for all K terms. The neighbour
+// the CSR row [p0, p1): every neighbouring x value is loaded once for all K terms. The CSR row is
+// read from LDS (stage_csr, after a barrier) when it fits, else from global memory; the neighbour
 // loads of kGatherBatch entries are issued together before they are used.
 constexpr int kGatherBatch = 4;
 template <typename T>
-__device__ inline void stage_gather(c2_t<T> (*dst)[2][kHalo], const c2_t<T>* __restrict__ xinst, const int* __restrict__ col,
+__device__ inline void stage_gather(TileLds<T>& L, const c2_t<T>* __restrict__ xinst, const int* __restrict__ col,
                                     const T* __restrict__ val, int p0, int p1, int K, int i0, int nr) {
   constexpr int hb = kHB;
   constexpr int w = kTileR + 2 * hb;
   const size_t cstride = (size_t)2 * nr;
+  const int n = p1 - p0;
+  const bool in_lds = n <= kGatherMax;
   for (int k = threadIdx.x; k < 2 * w; k += kThreads) {
     const int s = k / w, kk = k - s * w, gi = i0 - hb + kk;
     const bool in = gi >= 0 && gi < nr;
@@ -50,17 +105,18 @@ __device__ inline void stage_gather(c2_t<T> (*dst)[2][kHalo], const c2_t<T>* __r
     c2_t<T> acc[kMaxGroup];
 #pragma unroll
     for (int q = 0; q < kMaxGroup; ++q) acc[q] = cmk<T>(0, 0);
-    for (int pb = p0; pb < p1; pb += kGatherBatch) {
+    for (int pb = 0; pb < n; pb += kGatherBatch) {
       c2_t<T> xv[kGatherBatch];
 #pragma unroll
       for (int u = 0; u < kGatherBatch; ++u) {
-        const int p = pb + u < p1 ? pb + u : p1 - 1;
-        xv[u] = xinst[(size_t)col[p] * cstride + (size_t)s * nr + gic];
+        const int p = pb + u < n ? pb + u : n - 1;
+        const int c = in_lds ? L.gcol[p] : col[p0 + p];
+        xv[u] = xinst[(size_t)c * cstride + (size_t)s * nr + gic];
       }
 #pragma unroll
       for (int u = 0; u < kGatherBatch; ++u) {
-        if (pb + u < p1) {
-          const T* v = val + (size_t)(pb + u - p0) * K;
+        if (pb + u < n) {
+          const T* v = (in_lds ? L.gval : val) + (size_t)(pb + u) * K;
 #pragma unroll
           for (int q = 0; q < kMaxGroup; ++q)
             if (q < K) acc[q] = rfma<T>(v[q], xv[u], acc[q]);
@@ -69,7 +125,7 @@ __device__ inline void stage_gather(c2_t<T> (*dst)[2][kHalo], const c2_t<T>* __r
     }
 #pragma unroll
     for (int q = 0; q < kMaxGroup; ++q)
-      if (q < K) dst[q][s][kk] = in ? acc[q] : cmk<T>(0, 0);
+      if (q < K) L.ws[q][s][kk] = in ? acc[q] : cmk<T>(0, 0);
   }
 }
 
@@ -104,7 +160,7 @@ __device__ inline c2_t<T> ccontract(const CTaps<T>& t, const c2_t<T>* x, c2_t<T>
   return acc;
 }
 
-// coef_f: LDS array [n_terms] of coef_m * f_{field_m}(t) for this instance.
+// tl: the instance's term table in LDS (terms_to_lds).
 //
 // Latency structure: every global load of a phase is issued before its first use, and the
 // branches around loads depend only on the spinor component s, which is uniform over a wave
@@ -112,7 +168,7 @@ __device__ inline c2_t<T> ccontract(const CTaps<T>& t, const c2_t<T>* x, c2_t<T>
 // staging barrier is passed, coupling bands two terms at a time.
 template <typename T>
 __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict__ xinst, int j, int i0,
-                                   const double2* coef_f, TileLds<T>& L) {
+                                   const TermLds& tl, TileLds<T>& L) {
   constexpr int hb = kHB, nb = 2 * kHB + 1;
   const int nr = op.nr;
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kTileR);
@@ -125,19 +181,21 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
   out.sx = cmk<T>(0, 0);
   out.hx = cmk<T>(0, 0);
 
+  // first pattern group: its CSR row staged with the channel tile, its gather after one barrier
+  const bool g0 = op.n_groups > 0 && tl.g_live[0] != 0;
+  int g0_p0 = 0, g0_p1 = 0, g0_K = 0;
+  if (g0) {
+    g0_K = tl.g_first[1];
+    g0_p0 = op.g_rowptr[j];
+    g0_p1 = op.g_rowptr[j + 1];
+  }
+  const T* g0_val = g0 ? op.g_val + op.g_voff[0] + (size_t)(g0_p0 - op.g_rowptr[0]) * g0_K : nullptr;
   __syncthreads();
   stage_channel<T>(L.xs, xinst + (size_t)j * cstride, i0, nr);
-  if (op.n_groups > 0) {
-    const int K0 = op.g_first[1];
-    const int p0 = op.g_rowptr[j], p1 = op.g_rowptr[j + 1];
-    bool any = false;
-    for (int q = 0; q < K0; ++q) {
-      const double2 cf = coef_f[op.g_term[q]];
-      any = any || cf.x != 0.0 || cf.y != 0.0;
-    }
-    if (p0 != p1 && any)
-      stage_gather<T>(L.ws, xinst, op.g_col, op.g_val + op.g_voff[0] + (size_t)(p0 - op.g_rowptr[0]) * K0, p0, p1, K0,
-                      i0, nr);
+  if (g0 && g0_p0 != g0_p1) {
+    stage_csr<T>(L, op.g_col, g0_val, g0_p0, g0_p1, g0_K);
+    __syncthreads();
+    stage_gather<T>(L, xinst, op.g_col, g0_val, g0_p0, g0_p1, g0_K, i0, nr);
   }
 
   // ---- H0 / S / channel taps of this kappa block: the real tap blocks this thread needs are listed
@@ -155,13 +213,14 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
       if (k == ns) { sp[k] = ptr; sx2[k] = s2; sdst[k] = dst; sstr[k] = str; }
     ++ns;
   };
+  // slot pointers are uniform (block starts); the thread's point is added at the load
 #pragma unroll
   for (int s2 = 0; s2 < 2; ++s2) {
-    const size_t blk = ((size_t)kb * 4 + s * 2 + s2) * bstride + ic;
+    const size_t blk = ((size_t)kb * 4 + s * 2 + s2) * bstride;
     if (op.n_h > 0 && (op.pq_h || s2 == s)) add_slot(op.h_blk + blk, s2, 0, 1);
     if (op.n_s > 0 && (op.pq_s || s2 == s)) add_slot(op.s_blk + blk, s2, 2, 1);
     if (op.has_chan && (op.pq_chan || s2 == s)) {
-      const T* cp = reinterpret_cast<const T*>(op.h_chan + ((size_t)j * 4 + s * 2 + s2) * bstride + ic);
+      const T* cp = reinterpret_cast<const T*>(op.h_chan + ((size_t)j * 4 + s * 2 + s2) * bstride);
       add_slot(cp, s2, 0, 2);
       add_slot(cp + 1, s2, 1, 2);
     }
@@ -173,7 +232,7 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
     for (int k = 0; k < kTapRound; ++k) {
       const int sl = r * kTapRound + k;
       if (sl < ns) {
-        const T* p = sp[sl];
+        const T* p = sp[sl] + (size_t)ic * sstr[sl];
         const size_t dstep = (size_t)nr * sstr[sl];
 #pragma unroll
         for (int d = 0; d < nb; ++d) tt[k].v[d] = p[d * dstep];
@@ -196,19 +255,18 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
   // ---- coupling terms: stage the angular combinations of a pattern group, then the band
   // contractions, the bands of two terms loaded together
   for (int gidx = 0; gidx < op.n_groups; ++gidx) {
-    const int f0 = op.g_first[gidx], K = op.g_first[gidx + 1] - f0;
+    if (tl.g_live[gidx] == 0) continue;  // uniform over the work-group
+    const int f0 = tl.g_first[gidx], K = tl.g_first[gidx + 1] - f0;
     const int* rp = op.g_rowptr + (size_t)gidx * (op.nang + 1);
     const int p0 = rp[j], p1 = rp[j + 1];
-    bool any = false;
-    for (int q = 0; q < K; ++q) {
-      const double2 cf = coef_f[op.g_term[f0 + q]];
-      any = any || cf.x != 0.0 || cf.y != 0.0;
-    }
-    if (p0 == p1 || !any) continue;  // uniform over the work-group
+    if (p0 == p1) continue;
     // the first group is staged together with the channel tile above (one barrier less)
     if (gidx > 0) {
+      const T* gv = op.g_val + op.g_voff[gidx] + (size_t)(p0 - rp[0]) * K;
       __syncthreads();
-      stage_gather<T>(L.ws, xinst, op.g_col, op.g_val + op.g_voff[gidx] + (size_t)(p0 - rp[0]) * K, p0, p1, K, i0, nr);
+      stage_csr<T>(L, op.g_col, gv, p0, p1, K);
+      __syncthreads();
+      stage_gather<T>(L, xinst, op.g_col, gv, p0, p1, K, i0, nr);
       __syncthreads();
     }
 #pragma unroll
@@ -219,8 +277,8 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int q = q0 + h;
-          m[h] = q < K ? op.g_term[f0 + q] : 0;
-          mask[h] = q < K ? __builtin_amdgcn_readfirstlane((op.t_mask[m[h]] >> (2 * s)) & 3) : 0;
+          m[h] = q < K ? tl.g_term[f0 + q] : 0;
+          mask[h] = q < K ? (tl.g_mask[f0 + q] >> (2 * s)) & 3 : 0;
 #pragma unroll
           for (int s2 = 0; s2 < 2; ++s2)
             if ((mask[h] >> s2) & 1)
@@ -233,7 +291,7 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
 #pragma unroll
             for (int s2 = 0; s2 < 2; ++s2)
               if ((mask[h] >> s2) & 1) acc = contract<T>(tr[h][s2], &L.ws[q0 + h][s2][ii], acc);
-            const double2 cf = coef_f[m[h]];
+            const double2 cf = tl.coef_f[m[h]];
             out.hx = cfma<T>(cmk<T>((T)cf.x, (T)cf.y), acc, out.hx);
           }
         }

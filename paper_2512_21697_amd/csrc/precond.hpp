@@ -5,16 +5,20 @@
 // ordered q = 2 i + s (radial index, spinor component) so each block is banded with half-width
 // w = 2 hb + 1.
 //
-// The triangular solves are sequential in q. One wave solves one channel; the 2nr rows are split
-// into P <= 64 segments of m rows, one per lane:
-//   1. every lane substitutes through its segment with a zero boundary window and keeps the
+// The triangular solves are sequential in q. One work-group solves one channel; the 2nr rows are
+// split into P <= 256 segments of m >= w rows, one per thread:
+//   1. every thread substitutes through its segment with a zero boundary window and keeps the
 //      last (forward) / first (backward) w values;
-//   2. the true boundary windows are propagated segment to segment, t_p = g_p - T_p t_{p-1},
-//      with the w x w coupling matrices T_p precomputed at factorisation time (13 lanes, one row
-//      of T_p each);
-//   3. every lane substitutes through its segment again from its true boundary window.
-// Factor storage per block: LU[q][0..w-1] = L(q, q-1-k), LU[q][w] = 1 / U(q, q),
-// LU[q][w+1+k] = U(q, q+1+k); TL[p][w][w], TU[p][w][w].
+//   2. the true boundary windows follow from t_p = g_p - T_p t_{p-1} (w x w coupling matrices T_p
+//      precomputed at factorisation time), in two levels: within groups of kSegGroup segments
+//      (13 threads per group, groups in parallel, started from a zero window), then across the
+//      group boundaries with the precomputed group products C_p, and finally every window is
+//      corrected by C_p times the true boundary entering its group;
+//   3. every thread substitutes through its segment again from its true boundary window.
+// Factor storage per block, row q = p m + t of segment p: entry k of the row is LU[t][k][p] (the
+// segment index fastest, so the threads of a wave read consecutive addresses), with entries
+// 0..w-1 = L(q, q-1-k), w = 1 / U(q, q), w+1+k = U(q, q+1+k); TL, TU [p][c][r] = T_p(r, c);
+// CL, CU [r][c][p].
 #pragma once
 #include "common.hpp"
 
@@ -22,16 +26,27 @@ namespace tdde {
 
 constexpr int kPrecW = 13;        // 2 * hb + 1 for hb = 6 (order-7 B-splines)
 constexpr int kPrecStride = 2 * kPrecW + 1;
-constexpr int kMaxSeg = 64;
+constexpr int kMaxSeg = kThreads;   // one segment per thread of the work-group
+constexpr int kSegGroup = 16;       // segments per group of the two-level boundary propagation
+constexpr int kMaxSegGroups = kMaxSeg / kSegGroup;
 
 template <typename T> struct DevPrec {
   int n;                   // 2 * nr
   int m;                   // rows per segment (segments 0..P-2 have exactly m rows, m >= w)
   int P;                   // segments
   const int* block_of;     // [nang] factor block of channel j
-  const c2_t<T>* LU;       // [nblk][n][kPrecStride]
-  const c2_t<T>* TL;       // [nblk][P][w][w]
-  const c2_t<T>* TU;       // [nblk][P][w][w]
+  const c2_t<T>* LU;       // [nblk][m][kPrecStride][P]: entry k of row t of segment p
+  const c2_t<T>* TL;       // [nblk][P][w][w] transposed per segment: TL[p][c][r] = T_p(r, c)
+  const c2_t<T>* TU;       // [nblk][P][w][w] likewise
+  const c2_t<T>* CL;       // [nblk][w][w][P] lower group products
+  const c2_t<T>* CU;       // [nblk][w][w][P] upper group products
+};
+
+// LDS of one chain solve: the boundary window of every segment and the true boundary of every
+// segment group.
+template <typename T> struct ChainLds {
+  c2_t<T> win[kMaxSeg][kPrecW];
+  c2_t<T> u[kMaxSegGroups][kPrecW];
 };
 
 // Vector element of row q in the [s][i] layout of one channel.
@@ -70,11 +85,12 @@ template <typename T, int NC> struct RowOps {
 };
 
 template <typename T, int KIND, int MODE, int NC>
-__device__ inline void row_fetch(RowOps<T, NC>& ro, const c2_t<T>* LU, const ChainIO<T>& io, int nr, int q) {
+__device__ inline void row_fetch(RowOps<T, NC>& ro, const c2_t<T>* LU, const ChainIO<T>& io, int nr, int q, int t,
+                                 int P) {
   const size_t e = prow(q, nr);
-  const c2_t<T>* row = LU + (size_t)q * kPrecStride + (KIND <= SUB_L3 ? 0 : kPrecW);
+  const c2_t<T>* row = LU + ((size_t)t * kPrecStride + (KIND <= SUB_L3 ? 0 : kPrecW)) * P;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) ro.c[k] = row[k];
+  for (int k = 0; k < NC; ++k) ro.c[k] = row[(size_t)k * P];
   if (KIND == SUB_L1) {
     if constexpr (MODE == MODE_P) { ro.z0 = io.r[e]; ro.z1 = io.pz[e]; ro.z2 = io.v[e]; }
     else if constexpr (MODE == MODE_S) { ro.z0 = io.r[e]; ro.z2 = io.v[e]; }
@@ -108,16 +124,20 @@ __device__ inline c2_t<T> row_input(const RowOps<T, NC>& ro, const ChainIO<T>& i
 //   upper (U1, U3): rows descending, win[k] = x_{q+1+k}; x_q = (y_q - sum_k U(q, q+1+k) win[k]) / U(q,q)
 // Phase 1 kinds keep only the window (L1 also stores the formed input and accumulates |z|^2);
 // phase 3 kinds write the result into io.out.
+// LU: the block's factors offset to the calling thread's segment (entry stride P).
 template <typename T, int KIND, int MODE, int W>
-__device__ inline void substitute(const c2_t<T>* LU, const ChainIO<T>& io, int nr, int o, int len, c2_t<T> (&win)[W],
-                                  double& nrm2) {
+__device__ inline void substitute(const c2_t<T>* LU, int P, const ChainIO<T>& io, int nr, int o, int len,
+                                  c2_t<T> (&win)[W], double& nrm2) {
   constexpr bool lower = KIND <= SUB_L3;
   constexpr int NC = lower ? W : W + 1;
   constexpr int D = kChainAhead;
   RowOps<T, NC> ro[D];
 #pragma unroll
   for (int d = 0; d < D; ++d)
-    if (d < len) row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, lower ? o + d : o + len - 1 - d);
+    if (d < len) {
+      const int tt = lower ? d : len - 1 - d;
+      row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, o + tt, tt, P);
+    }
   for (int t0 = 0; t0 < len; t0 += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -141,7 +161,10 @@ __device__ inline void substitute(const c2_t<T>* LU, const ChainIO<T>& io, int n
         win[0] = acc;
         // loads of row t + D are issued before this row's stores, so waiting for them later does
         // not wait for the stores
-        if (t + D < len) row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, lower ? o + t + D : o + len - 1 - t - D);
+        if (t + D < len) {
+          const int tt = lower ? t + D : len - 1 - t - D;
+          row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, o + tt, tt, P);
+        }
         if (KIND == SUB_L1 && MODE != MODE_IN && MODE != MODE_IN_S) io.pz[e] = zin;
         if (KIND == SUB_L3 || KIND == SUB_U3) io.out[e] = acc;
       }
@@ -157,89 +180,171 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Boundary propagation over the segments: lane r < W owns row r of the w x w coupling matrices and
-// of the windows; the T row of the next step is loaded one step ahead.
-//   lower: t_p = g_p - T_p t_{p-1}, p = 1 .. P-1; upper: h_p = g_p - T_p h_{p+1}, p = P-2 .. 0.
+// Phase 2, first level: the recurrence inside every group of kSegGroup segments, started from the
+// group's own zero-window tail. Wave v owns groups 4v .. 4v+3; lane 13 k + r (k < 4) owns row r of
+// group 4v + k. The T row of the next step is loaded one step ahead.
+//   lower: t_p = g_p - T_p t_{p-1}, p ascending from the group's first segment;
+//   upper: h_p = g_p - T_p h_{p+1}, p descending from the group's last segment.
 template <typename T, bool LOWER, int W>
-__device__ inline void propagate(const c2_t<T>* Tm, int P, c2_t<T>* lds) {
-  const int lane = threadIdx.x & 63;
-  const int first = LOWER ? 1 : P - 2, count = P - 1;
+__device__ inline void group_recurrence(const c2_t<T>* Tm, int P, ChainLds<T>& L) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k = lane / W, r = lane - k * W;
+  const int g = wave * 4 + k;
+  const int lo = g * kSegGroup, hi = min(lo + kSegGroup - 1, P - 1);
+  const bool act = lane < 4 * W && lo < P;
   c2_t<T> tr[W];
-  if (lane < W && count > 0) {
+  auto fetch = [&](int step) {
+    const int p = LOWER ? lo + step : hi - step;
+    if (act && step < kSegGroup && (LOWER ? p <= hi : p >= lo)) {
 #pragma unroll
-    for (int c = 0; c < W; ++c) tr[c] = Tm[((size_t)first * W + lane) * W + c];
-  }
-  for (int k = 0; k < count; ++k) {
-    const int p = LOWER ? first + k : first - k;
-    const int prev = LOWER ? p - 1 : p + 1;
-    c2_t<T> acc = cmk<T>(0, 0);
-    if (lane < W) {
-      acc = lds[p * W + lane];
-#pragma unroll
-      for (int c = 0; c < W; ++c) acc = csub<T>(acc, cmul<T>(tr[c], lds[prev * W + c]));
-      if (k + 1 < count) {
-        const int pn = LOWER ? p + 1 : p - 1;
-#pragma unroll
-        for (int c = 0; c < W; ++c) tr[c] = Tm[((size_t)pn * W + lane) * W + c];
-      }
+      for (int c = 0; c < W; ++c) tr[c] = Tm[((size_t)p * W + c) * W + r];
     }
+  };
+  fetch(1);
+  for (int step = 1; step < kSegGroup; ++step) {
+    const int p = LOWER ? lo + step : hi - step;
+    const bool on = act && (LOWER ? p <= hi : p >= lo);
+    c2_t<T> acc = cmk<T>(0, 0);
+    if (on) {
+      const int prev = LOWER ? p - 1 : p + 1;
+      acc = L.win[p][r];
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc = csub<T>(acc, cmul<T>(tr[c], L.win[prev][c]));
+    }
+    fetch(step + 1);
     wave_sync();
-    if (lane < W) lds[p * W + lane] = acc;
+    if (on) L.win[p][r] = acc;
     wave_sync();
   }
 }
 
-// Solve M_blk z = input for one channel with one wave (the calling wave; lanes = segments).
-// lds: kMaxSeg * W complex values. Returns the |input|^2 sum of the chain (valid in lane 0).
+// Phase 2, second level (wave 0, lanes r < W): the true boundary of every group, in order,
+//   lower: u_0 = t_hi(0), u_G = t^loc_hi(G) + CL_hi(G) u_{G-1};
+//   upper: u_last = h_lo(last), u_G = h^loc_lo(G) + CU_lo(G) u_{G+1}.
+template <typename T, bool LOWER, int W>
+__device__ inline void group_boundaries(const c2_t<T>* Cm, int P, ChainLds<T>& L) {
+  const int r = threadIdx.x;
+  if (r >= W) return;
+  const int NG = (P + kSegGroup - 1) / kSegGroup;
+  const size_t cs = (size_t)P;  // stride between (row, column) planes of C
+  auto seg_of = [&](int G) { return LOWER ? min(G * kSegGroup + kSegGroup - 1, P - 1) : G * kSegGroup; };
+  const int G0 = LOWER ? 0 : NG - 1;
+  L.u[G0][r] = L.win[seg_of(G0)][r];
+  c2_t<T> cr[W];
+  auto fetch = [&](int G) {
+    if (G >= 0 && G < NG && G != G0) {
+      const int p = seg_of(G);
+#pragma unroll
+      for (int c = 0; c < W; ++c) cr[c] = Cm[((size_t)r * W + c) * cs + p];
+    }
+  };
+  fetch(LOWER ? 1 : NG - 2);
+  for (int step = 1; step < NG; ++step) {
+    const int G = LOWER ? step : NG - 1 - step;
+    const int Gin = LOWER ? G - 1 : G + 1;
+    wave_sync();
+    c2_t<T> acc = L.win[seg_of(G)][r];
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(cr[c], L.u[Gin][c]));
+    fetch(LOWER ? G + 1 : G - 1);
+    wave_sync();
+    L.u[G][r] = acc;
+  }
+}
+
+// True boundary window of segment q into out[W]: the group-local window corrected by the group
+// product times the true boundary entering the group (nothing to correct in the group where the
+// recurrence starts).
+template <typename T, bool LOWER, int W>
+__device__ inline void true_window(const c2_t<T>* Cm, int P, int q, const ChainLds<T>& L, c2_t<T> (&out)[W]) {
+  const int NG = (P + kSegGroup - 1) / kSegGroup;
+  const int G = q / kSegGroup;
+#pragma unroll
+  for (int c = 0; c < W; ++c) out[c] = L.win[q][c];
+  const bool corr = LOWER ? G > 0 : G < NG - 1;
+  if (corr) {
+    const c2_t<T>* ub = L.u[LOWER ? G - 1 : G + 1];
+    c2_t<T> uu[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) uu[c] = ub[c];
+#pragma unroll
+    for (int rr = 0; rr < W; ++rr) {
+      c2_t<T> acc = out[rr];
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(Cm[((size_t)rr * W + c) * P + q], uu[c]));
+      out[rr] = acc;
+    }
+  }
+}
+
+// Solve M_blk z = input for one channel with the whole work-group (all threads call it; one
+// segment per thread).
 template <typename T, int MODE>
-__device__ inline double chain_solve(const DevPrec<T>& pc, int blk, int nr, const ChainIO<T>& io, c2_t<T>* lds) {
+__device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int blk, int nr, const ChainIO<T>& io, ChainLds<T>& L) {
   constexpr int W = kPrecW;
-  const int lane = threadIdx.x & 63;
+  const int t = threadIdx.x;
   const int P = pc.P, m = pc.m, n = pc.n;
-  const c2_t<T>* LU = pc.LU + (size_t)blk * n * kPrecStride;
-  const c2_t<T>* TL = pc.TL + (size_t)blk * P * W * W;
-  const c2_t<T>* TU = pc.TU + (size_t)blk * P * W * W;
-  const int o = lane * m;
-  const int len = lane < P ? min(m, n - o) : 0;
-  double nrm2 = 0.0, dummy = 0.0;
-  c2_t<T> win[W];
+  const c2_t<T>* LU = pc.LU + (size_t)blk * m * kPrecStride * P + (t < P ? t : 0);
+  const size_t tsz = (size_t)P * W * W;
+  const c2_t<T>* TL = pc.TL + blk * tsz;
+  const c2_t<T>* TU = pc.TU + blk * tsz;
+  const c2_t<T>* CL = pc.CL + blk * tsz;
+  const c2_t<T>* CU = pc.CU + blk * tsz;
+  const int o = t * m;
+  const int len = t < P ? min(m, n - o) : 0;
+  double dummy = 0.0;
+  c2_t<T> win[W], tw[W];
 
   // ---- lower solve, phase 1: local windows; tail t_p[c] = y[o + len - W + c] = win[W-1-c]
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_L1, MODE, W>(LU, io, nr, o, len, win, nrm2);
-  if (lane < P) {
+  substitute<T, SUB_L1, MODE, W>(LU, P, io, nr, o, len, win, dummy);
+  __syncthreads();  // the previous solve's readers of L are done
+  if (t < P) {
 #pragma unroll
-    for (int c = 0; c < W; ++c) lds[lane * W + c] = win[W - 1 - c];
+    for (int c = 0; c < W; ++c) L.win[t][c] = win[W - 1 - c];
   }
-  wave_sync();
-  // ---- phase 2: true tails
-  propagate<T, true, W>(TL, P, lds);
+  __syncthreads();
+  // ---- phase 2: group recurrences, group boundaries
+  group_recurrence<T, true, W>(TL, P, L);
+  __syncthreads();
+  group_boundaries<T, true, W>(CL, P, L);
+  __syncthreads();
   // ---- phase 3: final substitution from the true window win[k] = y_{o-1-k} = t_{p-1}[W-1-k]
+  if (t > 0 && t < P) {
+    true_window<T, true, W>(CL, P, t - 1, L, tw);
 #pragma unroll
-  for (int k = 0; k < W; ++k) win[k] = (lane > 0 && lane < P) ? lds[(lane - 1) * W + (W - 1 - k)] : cmk<T>(0, 0);
-  wave_sync();
-  substitute<T, SUB_L3, MODE, W>(LU, io, nr, o, len, win, dummy);
+    for (int k = 0; k < W; ++k) win[k] = tw[W - 1 - k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
+  }
+  substitute<T, SUB_L3, MODE, W>(LU, P, io, nr, o, len, win, dummy);
 
   // ---- upper solve, phase 1: heads h_p[c] = x[o + c] = win[c] with zero incoming window
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_U1, MODE, W>(LU, io, nr, o, len, win, dummy);
-  if (lane < P) {
+  substitute<T, SUB_U1, MODE, W>(LU, P, io, nr, o, len, win, dummy);
+  __syncthreads();  // every thread has read its lower window
+  if (t < P) {
 #pragma unroll
-    for (int c = 0; c < W; ++c) lds[lane * W + c] = win[c];
+    for (int c = 0; c < W; ++c) L.win[t][c] = win[c];
   }
-  wave_sync();
-  // ---- phase 2: h_p = g_p - TU_p h_{p+1}, p descending
-  propagate<T, false, W>(TU, P, lds);
+  __syncthreads();
+  group_recurrence<T, false, W>(TU, P, L);
+  __syncthreads();
+  group_boundaries<T, false, W>(CU, P, L);
+  __syncthreads();
   // ---- phase 3: x from the true incoming window win[k] = x_{o+len+k} = h_{p+1}[k]
+  if (t + 1 < P) {
+    true_window<T, false, W>(CU, P, t + 1, L, tw);
 #pragma unroll
-  for (int k = 0; k < W; ++k) win[k] = lane + 1 < P ? lds[(lane + 1) * W + k] : cmk<T>(0, 0);
-  wave_sync();
-  substitute<T, SUB_U3, MODE, W>(LU, io, nr, o, len, win, dummy);
-  // |input|^2 of the chain
-  for (int off = 32; off > 0; off >>= 1) nrm2 += __shfl_xor(nrm2, off, 64);
-  return nrm2;
+    for (int k = 0; k < W; ++k) win[k] = tw[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
+  }
+  substitute<T, SUB_U3, MODE, W>(LU, P, io, nr, o, len, win, dummy);
 }
 
 }  // namespace tdde

@@ -94,7 +94,7 @@ struct Inst {
 
 template <typename T> union SharedLds {
   TileLds<T> tile;
-  c2_t<T> chain[kMaxSeg * kPrecW];
+  ChainLds<T> chain;
 };
 
 struct Shared {
@@ -103,7 +103,7 @@ struct Shared {
     SharedLds<float> f;
   } u;
   double red[2 * kThreads / 64];
-  double2 coef_f[kMaxTerms];
+  TermLds tl;
 };
 
 __device__ inline void put_partial(const SolveArgs& a, const WgInfo& wi, int slot, double2 v, Shared& sh) {
@@ -145,7 +145,7 @@ template <typename T> __device__ inline long tile_elem(const DevOp<T>& op, int j
   return i < op.nr ? (long)j * 2 * op.nr + (long)s * op.nr + i : -1;
 }
 
-// Chain loop: channel j of the instance handled by wave 0 of work-group (j % G).
+// Chain loop: channel j of the instance handled by work-group (j % G).
 #define FOR_CHAINS(op, wi) for (int j_ = (wi).g; j_ < (op).nang; j_ += (wi).G)
 
 template <typename T>
@@ -157,7 +157,7 @@ template <typename T, typename F>
 __device__ inline void apply_own(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
   const DevOp<T>& op = op_of<T>(a);
   FOR_TILES(op, wi) {
-    SH<T> r = apply_tile<T>(op, xin, j_, i0_, sh.coef_f, lds_of<T>(sh).tile);
+    SH<T> r = apply_tile<T>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile);
     const long e = tile_elem<T>(op, j_, i0_);
     if (e >= 0) f(e, r.sx, r.hx);
   }
@@ -180,29 +180,25 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
 }
 __device__ inline double2 dmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
-// Preconditioner chain phase for own channels (MODE_P / MODE_FRESH / MODE_IN_S).
+// Preconditioner chain phase for own channels (MODE_P / MODE_FRESH / MODE_IN_S); the whole
+// work-group solves one channel at a time.
 template <typename T, int MODE>
-__device__ inline double chains_own(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, size_t base, double2 c1,
-                                    double2 c2, Shared& sh) {
+__device__ inline void chains_own(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, size_t base, double2 c1,
+                                  double2 c2, Shared& sh) {
   const DevOp<T>& op = op_of<T>(a);
   const DevPrec<T>& pc = pc_of<T>(a);
-  double nrm2 = 0.0;
   FOR_CHAINS(op, wi) {
-    if (threadIdx.x < 64) {
-      const size_t cb = base + (size_t)j_ * 2 * op.nr;
-      ChainIO<T> io;
-      io.r = V.r + cb;
-      io.v = V.v + cb;
-      constexpr bool on_s = MODE == MODE_S || MODE == MODE_IN_S;
-      io.pz = (on_s ? V.s : V.p) + cb;
-      io.out = (on_s ? V.sh : V.ph) + cb;
-      io.c1 = c1;
-      io.c2 = c2;
-      const double n2 = chain_solve<T, MODE>(pc, pc.block_of[j_], op.nr, io, lds_of<T>(sh).chain);
-      if (threadIdx.x == 0) nrm2 += n2;
-    }
+    const size_t cb = base + (size_t)j_ * 2 * op.nr;
+    ChainIO<T> io;
+    io.r = V.r + cb;
+    io.v = V.v + cb;
+    constexpr bool on_s = MODE == MODE_S || MODE == MODE_IN_S;
+    io.pz = (on_s ? V.s : V.p) + cb;
+    io.out = (on_s ? V.sh : V.ph) + cb;
+    io.c1 = c1;
+    io.c2 = c2;
+    chain_solve<T, MODE>(pc, pc.block_of[j_], op.nr, io, lds_of<T>(sh).chain);
   }
-  return nrm2;  // valid in thread 0
 }
 
 // BiCGSTAB on A y = rhs for every live instance; y holds the initial guess, r = rhs - A y and
@@ -422,20 +418,12 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
 }
 
 __device__ inline void fields_to_lds(const SolveArgs& a, const WgInfo& wi, double t_mid, Shared& sh) {
-  __syncthreads();
-  const DevOp<double>& op = a.op64;
-  if (threadIdx.x < op.n_terms) {
-    const int m = threadIdx.x;
-    double f = 0.0;
-    if (wi.live) {
-      const int fi = op.t_field[m];
-      f = a.mode == MODE_STEP ? pulse_eval(a.pulses[(size_t)wi.b * a.n_fields + fi], t_mid)
-                              : a.fvals[(size_t)wi.b * a.n_fields + fi];
-    }
-    const double2 c = op.t_coef[m];
-    sh.coef_f[m] = make_double2(c.x * f, c.y * f);
-  }
-  __syncthreads();
+  terms_to_lds<double>(a.op64, sh.tl, [&](int m) {
+    if (!wi.live) return 0.0;
+    const int fi = a.op64.t_field[m];
+    return a.mode == MODE_STEP ? pulse_eval(a.pulses[(size_t)wi.b * a.n_fields + fi], t_mid)
+                               : a.fvals[(size_t)wi.b * a.n_fields + fi];
+  });
 }
 
 // After a grid-barrier time-out: report the unfinished steps of the instance as failed launches.

@@ -124,20 +124,15 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void apply_kernel(DevOp<T> op, const c2_t<T>* x, c2_t<T>* y, double2 as,
                                                          double2 ah, const double* fvals, int n_fields, int E) {
   __shared__ TileLds<T> L;
-  __shared__ double2 coef_f[kMaxTerms];
+  __shared__ TermLds tl;
   // radial tile fastest, then instance, then channel: work-group w runs on XCD w % 8 = tile % 8
   // (n_itiles a multiple of 8), so every instance and channel of a radial tile shares one L2 and
   // the instances of one tile run close together (operator bands reused from L2)
   const int it = blockIdx.x, b = blockIdx.y, j = blockIdx.z;
-  if (threadIdx.x < op.n_terms) {
-    const double f = fvals[(size_t)b * n_fields + op.t_field[threadIdx.x]];
-    const double2 c = op.t_coef[threadIdx.x];
-    coef_f[threadIdx.x] = make_double2(c.x * f, c.y * f);
-  }
-  __syncthreads();
+  terms_to_lds<T>(op, tl, [&](int m) { return fvals[(size_t)b * n_fields + op.t_field[m]]; });
   const c2_t<T>* xb = x + (size_t)b * E;
   const int i0 = it * kTileR;
-  SH<T> r = apply_tile<T>(op, xb, j, i0, coef_f, L);
+  SH<T> r = apply_tile<T>(op, xb, j, i0, tl, L);
   const int s = threadIdx.x / kTileR, i = i0 + (threadIdx.x - s * kTileR);
   if (i < op.nr) {
     c2_t<T> out = cmul<T>(to_c<T>(as), r.sx);
@@ -147,8 +142,8 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(DevOp<T> op, const c2_t
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void precond_kernel(DevPrec<T> pc, int nr, const c2_t<T>* in, c2_t<T>* out, int E) {
-  __shared__ c2_t<T> lds[kMaxSeg * kPrecW];
+__global__ __launch_bounds__(kThreads) void precond_kernel(DevPrec<T> pc, int nr, const c2_t<T>* in, c2_t<T>* out, int E) {
+  __shared__ ChainLds<T> lds;
   const int j = blockIdx.x, b = blockIdx.y;
   const size_t cb = (size_t)b * E + (size_t)j * 2 * nr;
   ChainIO<T> io;
@@ -482,7 +477,7 @@ tdde_status tdde_launch_info(tdde_ctx* c, int32_t* n_wg, int32_t* per_inst) {
 
 // Banded LU of M = S + i dt/2 H0 for one block, rows q = 2 i + s, plus segment coupling matrices.
 static void factor_block(const tdde_ctx* c, int j, double dt, int m, int P, std::vector<cd>& LU, std::vector<cd>& TL,
-                         std::vector<cd>& TU) {
+                         std::vector<cd>& TU, std::vector<cd>& CL, std::vector<cd>& CU) {
   const int nr = c->d.nr, hb = c->d.half_band, n = 2 * nr, w = 2 * hb + 1, ws = 2 * w + 1;
   const double kap = c->kappa[j];
   std::vector<cd> A((size_t)n * ws, cd(0, 0));  // A[q][k + w] = M(q, q + k)
@@ -556,6 +551,51 @@ static void factor_block(const tdde_ctx* c, int j, double dt, int m, int P, std:
         for (int cc = 0; cc < w; ++cc) TU[((size_t)p * w + rr) * w + cc] = W[(size_t)rr * w + cc];
     }
   }
+  // Group products for the two-level boundary propagation (segments in groups of kSegGroup):
+  // lower, p in group G >= 1 with first segment f = G * kSegGroup:
+  //   CL_p = (-T_p)(-T_{p-1}) ... (-T_f), so that t_p = t^loc_p + CL_p u_{G-1}
+  // (t^loc: the group's recurrence started from a zero window, u_{G-1}: true tail of the last
+  // segment of group G-1); upper likewise from the top segment of every group but the last.
+  auto mul_neg = [&](const cd* A, const cd* B, cd* C) {  // C = -A B (w x w)
+    for (int r = 0; r < w; ++r)
+      for (int cc = 0; cc < w; ++cc) {
+        cd acc(0, 0);
+        for (int k = 0; k < w; ++k) acc += A[r * w + k] * B[k * w + cc];
+        C[r * w + cc] = -acc;
+      }
+  };
+  std::vector<cd> CLp((size_t)P * w * w, cd(0, 0)), CUp((size_t)P * w * w, cd(0, 0));  // [p][w][w]
+  const int last_group = (P - 1) / kSegGroup;
+  for (int p = 0; p < P; ++p) {
+    const int G = p / kSegGroup;
+    if (G == 0) continue;
+    cd* dst = CLp.data() + (size_t)p * w * w;
+    const cd* T = TL.data() + (size_t)p * w * w;
+    if (p == G * kSegGroup) {
+      for (int k = 0; k < w * w; ++k) dst[k] = -T[k];
+    } else {
+      mul_neg(T, CLp.data() + (size_t)(p - 1) * w * w, dst);
+    }
+  }
+  for (int p = P - 1; p >= 0; --p) {
+    const int G = p / kSegGroup;
+    if (G == last_group) continue;
+    cd* dst = CUp.data() + (size_t)p * w * w;
+    const cd* T = TU.data() + (size_t)p * w * w;
+    if (p == G * kSegGroup + kSegGroup - 1) {
+      for (int k = 0; k < w * w; ++k) dst[k] = -T[k];
+    } else {
+      mul_neg(T, CUp.data() + (size_t)(p + 1) * w * w, dst);
+    }
+  }
+  // device layout [w][w][p]: threads of consecutive segments read consecutive entries
+  CL.assign((size_t)P * w * w, cd(0, 0));
+  CU.assign((size_t)P * w * w, cd(0, 0));
+  for (int p = 0; p < P; ++p)
+    for (int k = 0; k < w * w; ++k) {
+      CL[(size_t)k * P + p] = CLp[(size_t)p * w * w + k];
+      CU[(size_t)k * P + p] = CUp[(size_t)p * w * w + k];
+    }
 }
 
 tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
@@ -569,25 +609,43 @@ tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
   if (n < w) return TDDE_OK;
   const int m = std::max(w, (n + kMaxSeg - 1) / kMaxSeg);
   const int P = (n + m - 1) / m;
-  std::vector<cd> LU, TL, TU;
-  std::vector<cd> allLU((size_t)c->nblk * n * ws), allTL((size_t)c->nblk * P * w * w), allTU((size_t)c->nblk * P * w * w);
+  std::vector<cd> LU, TL, TU, CL, CU;
+  const size_t tsz = (size_t)P * w * w;
+  const size_t lsz = (size_t)m * ws * P;  // per block: [m][ws][P], segment index fastest
+  std::vector<cd> allLU(c->nblk * lsz, cd(0, 0)), allTL(c->nblk * tsz), allTU(c->nblk * tsz), allCL(c->nblk * tsz),
+      allCU(c->nblk * tsz);
   std::vector<int> rep(c->nblk, -1);
   for (int j = 0; j < c->d.nang; ++j)
     if (rep[c->block_of[j]] < 0) rep[c->block_of[j]] = j;
   for (int bk = 0; bk < c->nblk; ++bk) {
-    factor_block(c, rep[bk], dt, m, P, LU, TL, TU);
-    std::copy(LU.begin(), LU.end(), allLU.begin() + (size_t)bk * n * ws);
-    std::copy(TL.begin(), TL.end(), allTL.begin() + (size_t)bk * P * w * w);
-    std::copy(TU.begin(), TU.end(), allTU.begin() + (size_t)bk * P * w * w);
+    factor_block(c, rep[bk], dt, m, P, LU, TL, TU, CL, CU);
+    cd* lu = allLU.data() + bk * lsz;
+    for (int q = 0; q < n; ++q) {
+      const int sg = q / m, t = q - sg * m;
+      for (int k = 0; k < ws; ++k) lu[((size_t)t * ws + k) * P + sg] = LU[(size_t)q * ws + k];
+    }
+    // T_p stored transposed: [p][c][r]
+    for (int sg = 0; sg < P; ++sg)
+      for (int r = 0; r < w; ++r)
+        for (int cc = 0; cc < w; ++cc) {
+          allTL[bk * tsz + ((size_t)sg * w + cc) * w + r] = TL[((size_t)sg * w + r) * w + cc];
+          allTU[bk * tsz + ((size_t)sg * w + cc) * w + r] = TU[((size_t)sg * w + r) * w + cc];
+        }
+    std::copy(CL.begin(), CL.end(), allCL.begin() + bk * tsz);
+    std::copy(CU.begin(), CU.end(), allCU.begin() + bk * tsz);
   }
   tdde_status s;
   if (!c->prec_alloc) {
     if ((s = dev_alloc(c, (double2**)&c->pc64.LU, allLU.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (double2**)&c->pc64.TL, allTL.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (double2**)&c->pc64.TU, allTU.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (double2**)&c->pc64.CL, allCL.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (double2**)&c->pc64.CU, allCU.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (float2**)&c->pc32.LU, allLU.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (float2**)&c->pc32.TL, allTL.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (float2**)&c->pc32.TU, allTU.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (float2**)&c->pc32.CL, allCL.size())) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, (float2**)&c->pc32.CU, allCU.size())) != TDDE_OK) return s;
     if ((s = upload(c, (int**)&c->pc64.block_of, c->block_of.data(), c->block_of.size())) != TDDE_OK) return s;
     c->pc32.block_of = c->pc64.block_of;
     c->prec_alloc = true;
@@ -595,21 +653,19 @@ tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
   c->pc64.n = c->pc32.n = n;
   c->pc64.m = c->pc32.m = m;
   c->pc64.P = c->pc32.P = P;
-  HIP_TRY(c, hipMemcpy((void*)c->pc64.LU, allLU.data(), allLU.size() * sizeof(cd), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy((void*)c->pc64.TL, allTL.data(), allTL.size() * sizeof(cd), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy((void*)c->pc64.TU, allTU.data(), allTU.size() * sizeof(cd), hipMemcpyHostToDevice));
   auto tof = [](const std::vector<cd>& v) {
     std::vector<float> f(2 * v.size());
     for (size_t i = 0; i < v.size(); ++i) { f[2 * i] = (float)v[i].real(); f[2 * i + 1] = (float)v[i].imag(); }
     return f;
   };
-  std::vector<float> f;
-  f = tof(allLU);
-  HIP_TRY(c, hipMemcpy((void*)c->pc32.LU, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
-  f = tof(allTL);
-  HIP_TRY(c, hipMemcpy((void*)c->pc32.TL, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
-  f = tof(allTU);
-  HIP_TRY(c, hipMemcpy((void*)c->pc32.TU, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  const std::vector<cd>* host[] = {&allLU, &allTL, &allTU, &allCL, &allCU};
+  const void* dev64[] = {c->pc64.LU, c->pc64.TL, c->pc64.TU, c->pc64.CL, c->pc64.CU};
+  const void* dev32[] = {c->pc32.LU, c->pc32.TL, c->pc32.TU, c->pc32.CL, c->pc32.CU};
+  for (int k = 0; k < 5; ++k) {
+    HIP_TRY(c, hipMemcpy((void*)dev64[k], host[k]->data(), host[k]->size() * sizeof(cd), hipMemcpyHostToDevice));
+    const std::vector<float> f = tof(*host[k]);
+    HIP_TRY(c, hipMemcpy((void*)dev32[k], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
   return TDDE_OK;
 }
 
@@ -662,7 +718,7 @@ tdde_status tdde_precond_apply(tdde_ctx* c, const void* v, void* z) {
   if (!c || !v || !z) return fail(c, TDDE_ERR_ARG, "null argument");
   if (!c->dt_set || !c->prec_alloc) return fail(c, TDDE_ERR_STATE, "set_dt first (half_band 6 only)");
   if (v == z) return fail(c, TDDE_ERR_ARG, "input and output must differ");
-  hipLaunchKernelGGL(precond_kernel<double>, dim3(c->d.nang, c->d.batch), dim3(64), 0, c->stream, c->pc64, c->d.nr,
+  hipLaunchKernelGGL(precond_kernel<double>, dim3(c->d.nang, c->d.batch), dim3(kThreads), 0, c->stream, c->pc64, c->d.nr,
                      (const double2*)v, (double2*)z, c->E);
   HIP_TRY(c, hipGetLastError());
   return TDDE_OK;
