@@ -14,7 +14,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -33,28 +32,61 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_iteration(E, op_bytes, prec_bytes, precond):
-    """Minimal HBM bytes of one BiCGSTAB iteration of the fused solver (see the design notes):
-    19 vector passes of E complex128 values, two operator applies (operator coefficients read once
-    each), and two preconditioner solves (factors read once each, input and output vectors counted
-    in the vector passes)."""
-    vec = 19 * E * 16
-    return vec + 2 * op_bytes + (2 * prec_bytes if precond else 0)
-
-
 def operator_bytes(op):
+    """Operator data a matrix-free apply reads at least once: the kappa-polynomial H0 / S bands, the
+    coupling bands and angular values, the per-channel complex bands."""
     n = op.h_poly.size * 8 + op.s_poly.size * 8 + sum(t.r_band.size * 8 + t.a_val.size * 12 for t in op.terms)
     if op.h_chan is not None:
         n += op.h_chan.size * 16
     return n
 
 
-def prec_factor_bytes(op):
-    nr, nblk = op.nr, (op.nang if op.h_chan is not None else len(set(op.kappa.tolist())))
-    n = 2 * nr
+def apply_bytes(op):
+    """One apply: x read, y written, operator data read."""
+    return 2 * op.n_unknowns * 16 + operator_bytes(op)
+
+
+def prec_bytes(op):
+    """One block preconditioner solve: every channel's banded L and U factors (2 w + 1 complex
+    values per row) read once, input read and output written."""
     w = 2 * op.hb + 1
-    P = math.ceil(n / max(w, math.ceil(n / 64)))
-    return nblk * (n * (2 * w + 1) + 2 * P * w * w) * 16
+    return op.nang * 2 * op.nr * (2 * w + 1) * 16 + 2 * op.n_unknowns * 16
+
+
+def algorithmic_bytes_per_step(op, matvecs, iters):
+    """Minimal HBM bytes of one time step as the solver runs it: every operator apply counted in
+    `matvecs` (right-hand side, Krylov products, true-residual check), one preconditioner solve per
+    Krylov product (matvecs - 2), and 4 + 12 * iters plain vector passes (right-hand side, guess and
+    residual set-up; the BiCGSTAB vector updates and dot products of every iteration)."""
+    E = op.n_unknowns
+    nprec = max(0.0, matvecs - 2.0)
+    return matvecs * apply_bytes(op) + nprec * prec_bytes(op) + (4 + 12 * iters) * E * 16
+
+
+def source_hash():
+    """Hash of the kernel sources: measured counters are only reported for the kernels they were
+    taken from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2512_21697_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the persistent kernel from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "persistent_kernel_hydrogen_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d
 
 
 def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0):
@@ -195,13 +227,15 @@ def spmv_measure(P, torch, w, reps=20):
 
 
 def cpu_baseline(w, precond, budget_s=20.0):
-    """The oracle (CSR assembly once, preconditioned textbook BiCGSTAB per step) on the host cores."""
+    """The oracle (CSR assembly once, preconditioned textbook BiCGSTAB per step) on the host cores.
+    Returns (steps/s, steps, seconds, threads used = process CPU time / wall time)."""
     from oracle.assemble import Assembled
     from oracle.step import BlockPreconditioner, cn_step
     asm = Assembled(w.op)
     M = BlockPreconditioner(asm, w.dt) if precond else None
     psi = w.psi0[0]
     t0 = time.perf_counter()
+    c0 = time.process_time()
     n = 0
     while True:
         psi, st = cn_step(asm, w.pulses[0], w.t0 + n * w.dt, w.dt, psi, guess="prev", precond=M)
@@ -209,7 +243,8 @@ def cpu_baseline(w, precond, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s or n >= 50:
             break
     el = time.perf_counter() - t0
-    return n / el, n, el
+    cpu = time.process_time() - c0
+    return n / el, n, el, max(1, round(cpu / el))
 
 
 def main():
@@ -248,10 +283,14 @@ def main():
     # roofline of the persistent solver kernel (the only kernel of the timed region)
     kern_ms = sum(t for t, _ in launches) / max(1, len(launches))
     steps_per_launch = sum(n for _, n in launches) / max(1, len(launches))
-    opb, pcb = operator_bytes(w.op), prec_factor_bytes(w.op)
     it_mean = float(iters.mean())
-    bytes_step = (2 + 2) * E * 16 + 2 * opb + it_mean * algorithmic_bytes_per_iteration(E, opb, pcb, True)
+    bytes_step = algorithmic_bytes_per_step(w.op, float(mv.mean()), it_mean)
     achieved = bytes_step * steps_per_launch / (kern_ms * 1e-3) / 1e9
+    tr = measured_traffic()
+    traffic = None
+    if tr is not None:
+        traffic = (tr["fetch_kib_per_step"] * tr["fetch_scale"] + tr["write_kib_per_step"] * tr["write_scale"]) * 1024.0 \
+            * steps_per_launch
     res = {
         "metric": "TDDE steps/s (hydrogen dipole, preconditioned FP64 BiCGSTAB to 1e-12)",
         "value": 1000.0 / ms_step,
@@ -274,9 +313,10 @@ def main():
         "all_converged": ok,
         "max_true_rel_res": float(st["true_rel_res"].max()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "persistent_kernel", "kernel_ms_per_launch": kern_ms,
-                     "steps_per_launch": steps_per_launch, "alg_bytes_per_step": bytes_step},
+                     "steps_per_launch": steps_per_launch, "alg_bytes_per_launch": bytes_step * steps_per_launch,
+                     "alg_bytes_per_step": bytes_step, "source_hash": source_hash()},
     }
     if not args.no_mixed:
         _log("bench: mixed precision on the hydrogen operator")
@@ -289,18 +329,18 @@ def main():
         w3 = synthetic.config3()
         ms3 = spmv_measure(P, torch, w3)
         E3 = w3.op.n_unknowns
-        b3 = 2 * E3 * 16 + operator_bytes(w3.op)
+        b3 = apply_bytes(w3.op)
         res["spmv_beyond_dipole"] = {"ms": ms3, "alg_GBps": b3 / (ms3 * 1e-3) / 1e9,
                                      "frac_hbm": b3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, "alg_bytes": b3,
                                      "N": E3}
         del w3
     if not args.no_cpu:
         _log("bench: cpu oracle baseline")
-        rate, n, el = cpu_baseline(w, True, args.cpu_budget)
-        res["cpu_baseline"] = {"value": rate, "unit": "steps/s", "cores": os.cpu_count(), "kind": "oracle",
+        rate, n, el, threads = cpu_baseline(w, True, args.cpu_budget)
+        res["cpu_baseline"] = {"value": rate, "unit": "steps/s", "cores": threads, "kind": "oracle",
                                "sample": f"{n} steps of the same workload from the ground state "
                                          f"({el:.1f} s; CSR assembly and LU factorisation excluded; "
-                                         f"scipy CSR matvec single-threaded)"}
+                                         f"cores = process CPU time / wall time)"}
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 16
         a = torch.ones(n, dtype=torch.complex128, device="cuda:0")
