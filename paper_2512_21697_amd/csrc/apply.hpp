@@ -130,7 +130,8 @@ __device__ inline void stage_gather(TileLds<T>& L, const c2_t<T>* __restrict__ x
 }
 
 // Result of one tile apply for the calling thread: S x and H x at (j, s, i).
-template <typename T> struct SH { c2_t<T> sx, hx; };
+// With a second term table (TWO) also hx2 = H x at the second table's fields (H0 part shared).
+template <typename T> struct SH { c2_t<T> sx, hx, hx2; };
 
 // Radial band taps of one (s, s') block at the calling thread's point: b[d] = B[s][s'][d][i].
 template <typename T> struct Taps { T v[2 * kHB + 1]; };
@@ -166,9 +167,9 @@ __device__ inline c2_t<T> ccontract(const CTaps<T>& t, const c2_t<T>* x, c2_t<T>
 // branches around loads depend only on the spinor component s, which is uniform over a wave
 // (128 threads per component), so they are scalar branches: H0/S taps are loaded before the
 // staging barrier is passed, coupling bands two terms at a time.
-template <typename T>
+template <typename T, bool TWO = false>
 __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict__ xinst, int j, int i0,
-                                   const TermLds& tl, TileLds<T>& L) {
+                                   const TermLds& tl, TileLds<T>& L, const TermLds* tl2 = nullptr) {
   constexpr int hb = kHB, nb = 2 * kHB + 1;
   const int nr = op.nr;
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kTileR);
@@ -180,9 +181,11 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
   SH<T> out;
   out.sx = cmk<T>(0, 0);
   out.hx = cmk<T>(0, 0);
+  out.hx2 = cmk<T>(0, 0);
+  auto live_g = [&](int g) { return tl.g_live[g] != 0 || (TWO && tl2->g_live[g] != 0); };
 
   // first pattern group: its CSR row staged with the channel tile, its gather after one barrier
-  const bool g0 = op.n_groups > 0 && tl.g_live[0] != 0;
+  const bool g0 = op.n_groups > 0 && live_g(0);
   int g0_p0 = 0, g0_p1 = 0, g0_K = 0;
   if (g0) {
     g0_K = tl.g_first[1];
@@ -251,11 +254,12 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
     }
   }
   if (op.n_s == 0) out.sx = L.xs[s][ii + hb];
+  if (TWO) out.hx2 = out.hx;
 
   // ---- coupling terms: stage the angular combinations of a pattern group, then the band
   // contractions, the bands of two terms loaded together
   for (int gidx = 0; gidx < op.n_groups; ++gidx) {
-    if (tl.g_live[gidx] == 0) continue;  // uniform over the work-group
+    if (!live_g(gidx)) continue;  // uniform over the work-group
     const int f0 = tl.g_first[gidx], K = tl.g_first[gidx + 1] - f0;
     const int* rp = op.g_rowptr + (size_t)gidx * (op.nang + 1);
     const int p0 = rp[j], p1 = rp[j + 1];
@@ -293,6 +297,10 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
               if ((mask[h] >> s2) & 1) acc = contract<T>(tr[h][s2], &L.ws[q0 + h][s2][ii], acc);
             const double2 cf = tl.coef_f[m[h]];
             out.hx = cfma<T>(cmk<T>((T)cf.x, (T)cf.y), acc, out.hx);
+            if (TWO) {
+              const double2 cf2 = tl2->coef_f[m[h]];
+              out.hx2 = cfma<T>(cmk<T>((T)cf2.x, (T)cf2.y), acc, out.hx2);
+            }
           }
         }
       }

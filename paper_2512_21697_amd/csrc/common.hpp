@@ -122,8 +122,11 @@ struct GridBar {
   bool failed;
 };
 
-__device__ inline bool grid_barrier(GridBar& gb) {
+// watch: optional device counter read by thread 0 after the barrier (every work-group's updates
+// before the barrier are visible); its value is returned in *watch_val for the whole work-group.
+__device__ inline bool grid_barrier(GridBar& gb, const int* watch = nullptr, int* watch_val = nullptr) {
   __shared__ unsigned bar_ok;
+  __shared__ int watch_s;
   if (gb.failed) return false;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -163,10 +166,12 @@ __device__ inline bool grid_barrier(GridBar& gb) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // see every arrival's writes (all XCDs)
     }
     bar_ok = ok;
+    if (watch != nullptr) watch_s = __hip_atomic_load(watch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
   gb.gen++;
   if (bar_ok == 0u) gb.failed = true;
+  if (watch_val != nullptr) *watch_val = watch_s;
   return !gb.failed;
 }
 

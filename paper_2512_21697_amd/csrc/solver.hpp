@@ -24,12 +24,17 @@
 
 namespace tdde {
 
-enum { ST_INACTIVE = 0, ST_ACTIVE = 1, ST_VERIFY = 2, ST_DONE = 3, ST_FAILED = 4, ST_PENDING = 5, ST_BREAKDOWN = 6 };
+// ST_VERIFY: the true residual b - A x is formed in the next window; ST_VCHECK: it is tested in the
+// window after that (accept, or restart from it as ST_PENDING, which the next W0 picks up).
+enum { ST_INACTIVE = 0, ST_ACTIVE = 1, ST_VERIFY = 2, ST_DONE = 3, ST_FAILED = 4, ST_PENDING = 5, ST_BREAKDOWN = 6,
+       ST_VCHECK = 7 };
 // A slot is never read and written in the same barrier window by one instance.
 //   RHO, RR: written W4 (and W1 for VERIFY), read W0 (RR also W2 for VERIFY)
 //   AUX: ||r||^2 of a restart, written W0/W1/W2, read W0 when PENDING
 //   ORR, OBB: outer refinement residual / rhs norms (mixed precision)
-enum { SLOT_RHO = 0, SLOT_RR, SLOT_RV, SLOT_SS, SLOT_TS, SLOT_TT, SLOT_BB, SLOT_AUX, SLOT_ORR, SLOT_OBB, kSlots };
+// SLOT_N*: the next step's initial partials, formed with the residual check of the current step
+enum { SLOT_RHO = 0, SLOT_RR, SLOT_RV, SLOT_SS, SLOT_TS, SLOT_TT, SLOT_BB, SLOT_AUX, SLOT_ORR, SLOT_OBB, SLOT_NRHO,
+       SLOT_NRR, SLOT_NBB, kSlots };
 enum { GUESS_ZERO = 0, GUESS_PREV = 1, GUESS_GIVEN = 2 };
 enum { MODE_SOLVE = 0, MODE_STEP = 1 };
 
@@ -49,7 +54,8 @@ struct SolveArgs {
   DevPrec<float> pc32;
   KVec<double> v64;
   KVec<float> v32;
-  double2* bvec;          // right-hand side workspace (FP64)
+  double2* bvec;          // right-hand side workspace (FP64), even steps of a launch
+  double2* bvec2;         // right-hand side of odd steps (the next step's is formed during this one)
   double2* r64;           // outer residual (mixed precision)
   float2* rhs32;          // inner right-hand side (mixed precision)
   int B, G, E, n_wg;
@@ -88,6 +94,9 @@ struct WgInfo {
 
 struct Inst {
   int state, fresh, iters, matvecs, restarts, first;
+  int fused;       // the pending residual check also formed the next step's b, r, r^ and partials
+  int nofuse;      // a failed check: form only the true residual from now on
+  int next_ready;  // finished with the next step's initial data in place
   double2 rho, alpha, omega;
   double bb, target2, rel_res, true_rel_res;
 };
@@ -104,6 +113,7 @@ struct Shared {
   } u;
   double red[2 * kThreads / 64];
   TermLds tl;
+  TermLds tl2;  // fields of the next step (formed with the current step's residual check)
 };
 
 __device__ inline void put_partial(const SolveArgs& a, const WgInfo& wi, int slot, double2 v, Shared& sh) {
@@ -163,6 +173,17 @@ __device__ inline void apply_own(const SolveArgs& a, const WgInfo& wi, const c2_
   }
 }
 
+// Same with the next step's fields as well: f(e, S x, H x, H_next x).
+template <typename T, typename F>
+__device__ inline void apply_own2(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
+  const DevOp<T>& op = op_of<T>(a);
+  FOR_TILES(op, wi) {
+    SH<T> r = apply_tile<T, true>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile, &sh.tl2);
+    const long e = tile_elem<T>(op, j_, i0_);
+    if (e >= 0) f(e, r.sx, r.hx, r.hx2);
+  }
+}
+
 template <typename T, typename F>
 __device__ inline void elem_own(const SolveArgs& a, const WgInfo& wi, F&& f) {
   const DevOp<T>& op = op_of<T>(a);
@@ -203,13 +224,14 @@ __device__ inline void chains_own(const SolveArgs& a, const WgInfo& wi, const KV
 
 // BiCGSTAB on A y = rhs for every live instance; y holds the initial guess, r = rhs - A y and
 // r^ = r are already written and their partials (SLOT_RHO, SLOT_RR, SLOT_BB) stored; the
-// unfinished-instance counter *cnt already counts this instance. verify: confirm convergence
-// with the true residual (restart on failure).
+// unfinished-work-group counter *cnt already counts this work-group. verify: confirm convergence
+// with the true residual (restart on failure). On its final transition an instance writes its
+// iterate to dst (when not null) and its statistics to *so (when not null). The loop ends at the
+// first barrier after which no work-group of the launch is unfinished.
 template <typename T, bool PREC>
 __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, const c2_t<T>* rhs, size_t base,
                               double tol, int max_iter, bool verify, int* cnt, Inst& st, Shared& sh, Marks& mk,
-                              GridBar& gb) {
-  const DevOp<T>& op = op_of<T>(a);
+                              GridBar& gb, c2_t<T>* dst, StatsDev* so, c2_t<T>* bnext_buf, bool from_next) {
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<T> ahc = to_c<T>(ah);
   constexpr bool prec = PREC;
@@ -223,40 +245,128 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
   c2_t<T>* shv = V.sh + base;
   c2_t<T>* t = V.t + base;
   const c2_t<T>* b_ = rhs + base;
+  c2_t<T>* bnext = bnext_buf != nullptr ? bnext_buf + base : nullptr;
+
+  // final transition: write back, report, leave the unfinished count (zero_x: the next step starts
+  // from a zero guess)
+  auto finish = [&](int state, bool zero_x = false) {
+    st.state = state;
+    if (dst != nullptr || zero_x)
+      elem_own<T>(a, wi, [&](long e) {
+        if (dst != nullptr) dst[e] = x[e];
+        if (zero_x) x[e] = cmk<T>(0, 0);
+      });
+    if (so != nullptr && wi.g == 0 && threadIdx.x == 0) {
+      so->status = state == ST_DONE ? 0 : (state == ST_BREAKDOWN ? 2 : 1);
+      so->iters = st.iters;
+      so->matvecs = st.matvecs;
+      so->restarts = st.restarts;
+      so->outer_iters = 0;
+      so->rel_res = st.rel_res;
+      so->true_rel_res = st.true_rel_res;
+    }
+    counter_add(cnt, -1);
+  };
+  // converged on the recursive residual
+  auto converged = [&]() {
+    if (verify) {
+      st.state = ST_VERIFY;
+    } else {
+      st.true_rel_res = st.rel_res;
+      finish(ST_DONE);
+    }
+  };
+  // true-residual states, handled in whichever window comes next (s0: state at window entry)
+  auto verify_step = [&](int s0) {
+    if (s0 == ST_VERIFY) {
+      if (bnext != nullptr && !st.nofuse) {
+        // true residual of this step (its norm) together with the next step's right-hand side
+        // b' = (S - i dt/2 H') x, residual r' = b' - A' x0 and r^' = r' (H': next step's fields)
+        double2 acc = make_double2(0.0, 0.0), accb = make_double2(0.0, 0.0), accr = make_double2(0.0, 0.0);
+        const c2_t<T> mahc = cmk<T>(-ahc.x, -ahc.y), mdt = cmk<T>(0, (T)(-a.dt));
+        const bool prev = a.guess == GUESS_PREV;
+        apply_own2<T>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx, c2_t<T> hx2) {
+          const c2_t<T> rt = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
+          dot_acc(acc, rt, rt);
+          const c2_t<T> bn = cfma<T>(mahc, hx2, sx);
+          bnext[e] = bn;
+          dot_acc(accb, bn, bn);
+          const c2_t<T> rn = prev ? cmul<T>(mdt, hx2) : bn;  // x0 = x: b' - A' x = -i dt H' x
+          r[e] = rn;
+          rh[e] = rn;
+          dot_acc(accr, rn, rn);
+        });
+        put_partial(a, wi, SLOT_RR, acc, sh);
+        put_partial(a, wi, SLOT_NBB, accb, sh);
+        put_partial(a, wi, SLOT_NRHO, accr, sh);
+        put_partial(a, wi, SLOT_NRR, accr, sh);
+        st.fused = 1;
+      } else {
+        double2 acc = make_double2(0.0, 0.0);
+        apply_own<T>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+          const c2_t<T> rr = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
+          r[e] = rr;
+          dot_acc(acc, rr, rr);
+        });
+        put_partial(a, wi, SLOT_RR, acc, sh);
+        put_partial(a, wi, SLOT_AUX, acc, sh);
+        st.fused = 0;
+      }
+      st.matvecs++;
+      st.state = ST_VCHECK;
+    } else if (s0 == ST_VCHECK) {
+      const double rr = get_total(a, wi, SLOT_RR, sh).x;
+      st.true_rel_res = st.bb > 0 ? sqrt(rr / st.bb) : 0.0;
+      if (rr <= st.target2) {
+        st.next_ready = st.fused;
+        finish(ST_DONE, st.fused && a.guess == GUESS_ZERO);
+      } else if (st.iters >= max_iter) {
+        finish(ST_FAILED);
+      } else if (st.fused) {
+        st.nofuse = 1;  // r now holds the next step's residual: form this step's again, then restart
+        st.state = ST_VERIFY;
+      } else {
+        st.state = ST_PENDING;  // true residual too large: restart from it (AUX holds ||r||^2)
+        st.restarts++;
+        elem_own<T>(a, wi, [&](long e) { rh[e] = r[e]; });
+      }
+    }
+  };
+
   while (true) {
+    int left = 0;  // work-groups of the launch still unfinished after the barrier
     // ---------------- W0
-    if (!grid_barrier(gb)) return;
+    if (!grid_barrier(gb, cnt, &left)) return;
+    if (left == 0) break;
     mk.mark(10);
+    int s0 = wi.live ? st.state : ST_INACTIVE;
     bool work = false;
     double2 beta = make_double2(0.0, 0.0);
-    if (wi.live && (st.state == ST_ACTIVE || st.state == ST_PENDING)) {
-      const bool pend = st.state == ST_PENDING;
-      const double2 rho = get_total(a, wi, pend ? SLOT_AUX : SLOT_RHO, sh);
-      const double rr = pend ? rho.x : get_total(a, wi, SLOT_RR, sh).x;
+    if (s0 == ST_ACTIVE || s0 == ST_PENDING) {
+      const bool pend = s0 == ST_PENDING;
+      const bool nx = st.first && from_next;  // initial partials formed by the previous step
+      const double2 rho = get_total(a, wi, pend ? SLOT_AUX : (nx ? SLOT_NRHO : SLOT_RHO), sh);
+      const double rr = pend ? rho.x : get_total(a, wi, nx ? SLOT_NRR : SLOT_RR, sh).x;
       if (st.first) {
-        st.bb = get_total(a, wi, SLOT_BB, sh).x;
+        st.bb = get_total(a, wi, nx ? SLOT_NBB : SLOT_BB, sh).x;
         st.target2 = tol * tol * st.bb;
         st.first = 0;
       }
       st.rel_res = st.bb > 0 ? sqrt(rr / st.bb) : 0.0;
-      if (st.state == ST_PENDING) { st.state = ST_ACTIVE; st.fresh = 1; }
+      if (pend) { st.state = ST_ACTIVE; st.fresh = 1; }
       if (rr <= st.target2) {
-        st.state = verify ? ST_VERIFY : ST_DONE;
-        if (!verify) { st.true_rel_res = st.rel_res; counter_add(cnt, -1); }
+        converged();
       } else if (st.iters >= max_iter) {
-        st.state = ST_FAILED;
-        counter_add(cnt, -1);
+        finish(ST_FAILED);
       } else {
         const double rn = sqrt(rho.x * rho.x + rho.y * rho.y);
         const double om = sqrt(st.omega.x * st.omega.x + st.omega.y * st.omega.y);
         if (!st.fresh && (rn <= 1e-300 * (1.0 + rr) || om == 0.0)) {
-          // breakdown: restart with r^ = r
+          // breakdown: restart from the same r with r^ = r; rho of the restart is ||r||^2
           st.restarts++;
           if (st.restarts > 20) {
-            st.state = ST_BREAKDOWN;
-            counter_add(cnt, -1);
+            finish(ST_BREAKDOWN);
           } else {
-            // restart from the same r with r^ = r; rho of the restart is ||r||^2
             st.state = ST_PENDING;
             double2 acc = make_double2(0.0, 0.0);
             elem_own<T>(a, wi, [&](long e) { rh[e] = r[e]; dot_acc(acc, r[e], r[e]); });
@@ -282,11 +392,13 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       }
       st.fresh = 0;
     }
-    // ---------------- W1
-    if (!grid_barrier(gb)) return;
+    verify_step(s0);
+    // ---------------- W1: v = A p^, <r^, v>
+    if (!grid_barrier(gb, cnt, &left)) return;
+    if (left == 0) break;
     mk.mark(11);
-    if (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
-    if (wi.live && st.state == ST_ACTIVE) {
+    s0 = wi.live ? st.state : ST_INACTIVE;
+    if (s0 == ST_ACTIVE) {
       double2 acc = make_double2(0.0, 0.0);
       apply_own<T>(a, wi, prec ? ph : p, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
         const c2_t<T> vv = cfma<T>(ahc, hx, sx);
@@ -295,21 +407,14 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       });
       put_partial(a, wi, SLOT_RV, acc, sh);
       st.matvecs++;
-    } else if (wi.live && st.state == ST_VERIFY) {
-      double2 acc = make_double2(0.0, 0.0);
-      apply_own<T>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
-        const c2_t<T> rr = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
-        r[e] = rr;
-        dot_acc(acc, rr, rr);
-      });
-      put_partial(a, wi, SLOT_RR, acc, sh);
-      put_partial(a, wi, SLOT_AUX, acc, sh);
-      st.matvecs++;
     }
-    // ---------------- W2
-    if (!grid_barrier(gb)) return;
+    verify_step(s0);
+    // ---------------- W2: alpha, s = r - alpha v, ||s||^2
+    if (!grid_barrier(gb, cnt, &left)) return;
+    if (left == 0) break;
     mk.mark(12);
-    if (wi.live && st.state == ST_ACTIVE) {
+    s0 = wi.live ? st.state : ST_INACTIVE;
+    if (s0 == ST_ACTIVE) {
       const double2 rv = get_total(a, wi, SLOT_RV, sh);
       if (rv.x == 0.0 && rv.y == 0.0) {
         st.state = ST_PENDING;  // breakdown: restart at the next W0 from the same r
@@ -319,8 +424,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         put_partial(a, wi, SLOT_AUX, acc, sh);
       } else {
         st.alpha = cdiv(st.rho, rv);
-        // s = r - alpha v and ||s||^2; the preconditioned s^ is formed only if the half step does
-        // not already converge (next window)
+        // the preconditioned s^ is formed only if the half step does not already converge (W3)
         double n2 = 0.0;
         const c2_t<T> al = to_c<T>(st.alpha);
         elem_own<T>(a, wi, [&](long e) {
@@ -330,26 +434,14 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         });
         put_partial(a, wi, SLOT_SS, make_double2(n2, 0.0), sh);
       }
-    } else if (wi.live && st.state == ST_VERIFY) {
-      const double rr = get_total(a, wi, SLOT_RR, sh).x;
-      st.true_rel_res = st.bb > 0 ? sqrt(rr / st.bb) : 0.0;
-      if (rr <= st.target2) {
-        st.state = ST_DONE;
-        counter_add(cnt, -1);
-      } else if (st.iters >= max_iter) {
-        st.state = ST_FAILED;
-        counter_add(cnt, -1);
-      } else {
-        st.state = ST_PENDING;  // true residual too large: restart from it (AUX holds ||r||^2)
-        st.restarts++;
-        elem_own<T>(a, wi, [&](long e) { rh[e] = r[e]; });
-      }
     }
-    // ---------------- W3
-    if (!grid_barrier(gb)) return;
+    verify_step(s0);
+    // ---------------- W3: half-step test; s^ = M^-1 s (preconditioned) or t = A s
+    if (!grid_barrier(gb, cnt, &left)) return;
+    if (left == 0) break;
     mk.mark(13);
-    bool half_done = false;
-    if (wi.live && st.state == ST_ACTIVE) {
+    s0 = wi.live ? st.state : ST_INACTIVE;
+    if (s0 == ST_ACTIVE) {
       const double ss = get_total(a, wi, SLOT_SS, sh).x;
       if (ss <= st.target2) {
         const c2_t<T> al = to_c<T>(st.alpha);
@@ -357,9 +449,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         elem_own<T>(a, wi, [&](long e) { x[e] = cfma<T>(al, dir[e], x[e]); });
         st.iters++;
         st.rel_res = st.bb > 0 ? sqrt(ss / st.bb) : 0.0;
-        st.state = verify ? ST_VERIFY : ST_DONE;
-        if (!verify) { st.true_rel_res = st.rel_res; counter_add(cnt, -1); }
-        half_done = true;
+        converged();
       } else if constexpr (PREC) {
         chains_own<T, MODE_IN_S>(a, wi, V, base, st.alpha, st.alpha, sh);  // s^ = K^-1 s
       } else {
@@ -375,11 +465,14 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         st.matvecs++;
       }
     }
+    verify_step(s0);
     if constexpr (PREC) {
       // ---------------- W3b: t = A s^
-      if (!grid_barrier(gb)) return;
+      if (!grid_barrier(gb, cnt, &left)) return;
+      if (left == 0) break;
       mk.mark(15);
-      if (wi.live && st.state == ST_ACTIVE && !half_done) {
+      s0 = wi.live ? st.state : ST_INACTIVE;
+      if (s0 == ST_ACTIVE) {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
         apply_own<T>(a, wi, shv, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
           const c2_t<T> tv = cfma<T>(ahc, hx, sx);
@@ -391,11 +484,14 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         put_partial(a, wi, SLOT_TT, tt, sh);
         st.matvecs++;
       }
+      verify_step(s0);
     }
-    // ---------------- W4
-    if (!grid_barrier(gb)) return;
+    // ---------------- W4: omega, x, r, <r^, r>, ||r||^2
+    if (!grid_barrier(gb, cnt, &left)) return;
+    if (left == 0) break;
     mk.mark(14);
-    if (wi.live && st.state == ST_ACTIVE && !half_done) {
+    s0 = wi.live ? st.state : ST_INACTIVE;
+    if (s0 == ST_ACTIVE) {
       const double2 ts = get_total(a, wi, SLOT_TS, sh);
       const double tt = get_total(a, wi, SLOT_TT, sh).x;
       st.omega = tt > 0.0 ? make_double2(ts.x / tt, ts.y / tt) : make_double2(0.0, 0.0);
@@ -414,11 +510,13 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       put_partial(a, wi, SLOT_RR, rr, sh);
       st.iters++;
     }
+    verify_step(s0);
   }
 }
 
-__device__ inline void fields_to_lds(const SolveArgs& a, const WgInfo& wi, double t_mid, Shared& sh) {
-  terms_to_lds<double>(a.op64, sh.tl, [&](int m) {
+__device__ inline void fields_to_lds(const SolveArgs& a, const WgInfo& wi, double t_mid, Shared& sh,
+                                     TermLds* dst = nullptr) {
+  terms_to_lds<double>(a.op64, dst != nullptr ? *dst : sh.tl, [&](int m) {
     if (!wi.live) return 0.0;
     const int fi = a.op64.t_field[m];
     return a.mode == MODE_STEP ? pulse_eval(a.pulses[(size_t)wi.b * a.n_fields + fi], t_mid)
@@ -452,6 +550,7 @@ void persistent_kernel(SolveArgs a) {
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<double> ahc = ah, mahc = make_double2(0.0, -0.5 * a.dt);
 
+  bool ready = false;  // this step's b, x0, r, r^ and partials were formed by the previous step
   for (int k = 0; k < a.n_chunk; ++k) {
     const int step = a.step0 + k;
     int* cnt = a.counters + (size_t)k * kCounterPerStep;
@@ -462,6 +561,19 @@ void persistent_kernel(SolveArgs a) {
     wk.live = inst;
     const double t_mid = a.t0 + (double)step * a.dt + 0.5 * a.dt;
     fields_to_lds(a, wk, t_mid, sh);
+    // the residual check of this step also forms the next step's right-hand side when the next
+    // step runs in this launch for this instance
+    const bool next_live = wi.live && k + 1 < a.n_chunk && (a.n_steps == nullptr || step + 1 < a.n_steps[wi.b]);
+    const bool fuse = !MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN && inst && next_live;
+    if (!MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN) {
+      WgInfo wn = wi;
+      wn.live = fuse;
+      fields_to_lds(a, wn, t_mid + a.dt, sh, &sh.tl2);
+    }
+    if (!inst) ready = false;
+    // right-hand side buffers alternate between steps so the next one can be formed early
+    double2* bbuf = (!MIXED && (k & 1)) ? a.bvec2 : a.bvec;
+    double2* bnbuf = (k & 1) ? a.bvec : a.bvec2;
 
     Inst st = {};
     st.state = inst ? ST_ACTIVE : ST_INACTIVE;
@@ -473,9 +585,9 @@ void persistent_kernel(SolveArgs a) {
 
     KVec<double> V = a.v64;
     double2* x = V.x + base;
-    double2* bv = a.bvec + base;
+    double2* bv = bbuf + base;
     // ---- right-hand side b = (S - i dt/2 H) psi and the initial guess
-    if (inst) {
+    if (inst && !ready) {
       if (a.mode == MODE_STEP) {
         double2 bb = {0, 0}, rr = {0, 0};
         const double2* psi = a.psi + base;
@@ -536,7 +648,12 @@ void persistent_kernel(SolveArgs a) {
 
     if constexpr (!MIXED) {
       if (inst) counter_add(cnt, 1);
-      krylov<double, PREC>(a, wk, V, a.bvec, base, a.tol, a.max_iter, true, cnt, st, sh, mk, gb);
+      double2* dst = (a.mode == MODE_STEP ? a.psi : a.x_io) + base;
+      StatsDev* so = a.stats != nullptr ? a.stats + (size_t)k * a.B + wk.b : nullptr;
+      krylov<double, PREC>(a, wk, V, bbuf, base, a.tol, a.max_iter, true, cnt, st, sh, mk, gb, dst, so,
+                           fuse ? bnbuf : nullptr, ready);
+      ready = inst && st.next_ready;
+      if (gb.failed) { fail_steps(a, wi, k); return; }
     } else {
       // ---- FP64 iterative refinement around an FP32 BiCGSTAB (inner residuals, dots in FP64)
       KVec<float> U = a.v32;
@@ -589,7 +706,8 @@ void persistent_kernel(SolveArgs a) {
         if (__hip_atomic_load(ocnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
         WgInfo wq = wk;
         wq.live = ist.state == ST_ACTIVE;
-        krylov<float, PREC>(a, wq, U, a.rhs32, base, a.inner_tol, a.max_iter, false, icnt, ist, sh, mk, gb);
+        krylov<float, PREC>(a, wq, U, a.rhs32, base, a.inner_tol, a.max_iter, false, icnt, ist, sh, mk, gb, nullptr,
+                            nullptr, nullptr, false);
         total_iters += ist.iters;
         total_mv += ist.matvecs;
         // x += ||r|| d (FP64), then r = b - A x (FP64)
@@ -618,23 +736,23 @@ void persistent_kernel(SolveArgs a) {
       st.matvecs = total_mv;
       st.state = outer_state == ST_DONE ? ST_DONE : (outer_state == ST_INACTIVE ? ST_INACTIVE : ST_FAILED);
       st.restarts = outer;  // reported as outer iterations below
-    }
 
-    // ---- write back and statistics
-    if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
-    mk.mark(2);
-    if (inst) {
-      double2* dst = a.mode == MODE_STEP ? a.psi + base : a.x_io + base;
-      elem_own<double>(a, wk, [&](long e) { dst[e] = x[e]; });
-      if (a.stats != nullptr && wk.g == 0 && threadIdx.x == 0) {
-        StatsDev& o = a.stats[(size_t)k * a.B + wk.b];
-        o.status = st.state == ST_DONE ? 0 : (st.state == ST_BREAKDOWN ? 2 : 1);
-        o.iters = st.iters;
-        o.matvecs = st.matvecs;
-        o.restarts = MIXED ? 0 : st.restarts;
-        o.outer_iters = MIXED ? st.restarts : 0;
-        o.rel_res = st.rel_res;
-        o.true_rel_res = st.true_rel_res;
+      // ---- write back and statistics (the FP64 path does both as each instance finishes)
+      if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
+      mk.mark(2);
+      if (inst) {
+        double2* dst = a.mode == MODE_STEP ? a.psi + base : a.x_io + base;
+        elem_own<double>(a, wk, [&](long e) { dst[e] = x[e]; });
+        if (a.stats != nullptr && wk.g == 0 && threadIdx.x == 0) {
+          StatsDev& o = a.stats[(size_t)k * a.B + wk.b];
+          o.status = st.state == ST_DONE ? 0 : (st.state == ST_BREAKDOWN ? 2 : 1);
+          o.iters = st.iters;
+          o.matvecs = st.matvecs;
+          o.restarts = 0;
+          o.outer_iters = st.restarts;
+          o.rel_res = st.rel_res;
+          o.true_rel_res = st.true_rel_res;
+        }
       }
     }
   }

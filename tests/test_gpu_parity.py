@@ -255,3 +255,43 @@ def test_bad_buffer_rejected_before_launch(gpu):
     x = torch.zeros(10, dtype=torch.complex128, device=DEV)
     with pytest.raises(ValueError):
         s.apply(x, x.clone())
+
+
+@pytest.mark.parametrize("case", ["h_prev", "c1_prev", "c1_zero", "c1_tight"])
+def test_multistep_launch_matches_oracle(gpu, case):
+    """Several steps in one persistent launch: every step after the first takes its right-hand side
+    from the previous step's residual check (one shared operator pass). The final state is compared
+    with the oracle's chain of steps (errors accumulate over the steps). "c1_tight" asks for a
+    relative residual of 1e-16, below what FP64 reaches, so checks fail and restart: the launch must
+    still end, with every step converged or NOT_CONVERGED and the state close to the oracle's."""
+    P = _lib()
+    if case == "h_prev":
+        w = dkb.config2(nr=300, r_max=60.0, lmax=3, driven=True, E0=0.5)
+        precond, guess, n, tol, max_iter = 1, P.GUESS_PREV, 6, 1e-12, 100
+    else:
+        w = synthetic.config1(driven=True)
+        precond, guess, n = 0, (P.GUESS_ZERO if case == "c1_zero" else P.GUESS_PREV), 8
+        tol, max_iter = (1e-16, 25) if case == "c1_tight" else (1e-12, 300)
+    s = P.Solver(w.op, 1)
+    s.set_dt(w.dt)
+    s.set_pulses(w.pulses)
+    psi = _dev(w.psi0).reshape(-1).clone()
+    stats = torch.zeros(n * 40, dtype=torch.uint8, device=DEV)
+    s.run_batched(psi, w.t0, 0, n, np.array([n], dtype=np.int32),
+                  P.solve_opts(tol=tol, max_iter=max_iter, guess=guess, precond=precond), stats)
+    torch.cuda.synchronize()
+    st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+    got = psi.cpu().numpy().reshape(w.op.nang, 2, w.op.nr)
+    assert np.all(np.isfinite(got))
+    asm = Assembled(w.op)
+    ref = w.psi0[0]
+    for k in range(n):
+        ref, _ = cn_step(asm, w.pulses[0], w.t0 + k * w.dt, w.dt, ref, solver="splu" if precond else "dense")
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    if case == "c1_tight":
+        assert set(st["status"].tolist()) <= {0, 1}, st["status"]
+        assert err < 1e-10 * n, err
+    else:
+        assert np.all(st["status"] == 0), st
+        assert np.all(st["true_rel_res"] <= tol), st["true_rel_res"]
+        assert err < 1e-10 * n, err
