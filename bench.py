@@ -53,14 +53,14 @@ def prec_bytes(op):
     return op.nang * 2 * op.nr * (2 * w + 1) * 16 + 2 * op.n_unknowns * 16
 
 
-def algorithmic_bytes_per_step(op, matvecs, iters):
+def algorithmic_bytes_per_step(op, matvecs, precs, iters):
     """Minimal HBM bytes of one time step as the solver runs it: every operator apply counted in
-    `matvecs` (right-hand side, Krylov products, true-residual check), one preconditioner solve per
-    Krylov product (matvecs - 2), and 4 + 12 * iters plain vector passes (right-hand side, guess and
-    residual set-up; the BiCGSTAB vector updates and dot products of every iteration)."""
+    `matvecs` (Krylov products, the true-residual check, which also forms the next step's right-hand
+    side), every preconditioner solve counted in `precs`, and 4 + 12 * iters plain vector passes
+    (right-hand side, guess and residual set-up; the BiCGSTAB vector updates and dot products of
+    every iteration)."""
     E = op.n_unknowns
-    nprec = max(0.0, matvecs - 2.0)
-    return matvecs * apply_bytes(op) + nprec * prec_bytes(op) + (4 + 12 * iters) * E * 16
+    return matvecs * apply_bytes(op) + precs * prec_bytes(op) + (4 + 12 * iters) * E * 16
 
 
 def source_hash():
@@ -284,7 +284,7 @@ def main():
     kern_ms = sum(t for t, _ in launches) / max(1, len(launches))
     steps_per_launch = sum(n for _, n in launches) / max(1, len(launches))
     it_mean = float(iters.mean())
-    bytes_step = algorithmic_bytes_per_step(w.op, float(mv.mean()), it_mean)
+    bytes_step = algorithmic_bytes_per_step(w.op, float(mv.mean()), float(st["precs"].mean()), it_mean)
     achieved = bytes_step * steps_per_launch / (kern_ms * 1e-3) / 1e9
     tr = measured_traffic()
     traffic = None
@@ -310,6 +310,7 @@ def main():
                    "batch": 1, "seq_len": None, "parallelism": "single GPU"},
         "iters_per_step": it_mean,
         "matvecs_per_step": float(mv.mean()),
+        "precond_solves_per_step": float(st["precs"].mean()),
         "all_converged": ok,
         "max_true_rel_res": float(st["true_rel_res"].max()),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

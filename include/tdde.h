@@ -113,10 +113,11 @@ typedef struct {
   int32_t status;       /* tdde_status of this instance; TDDE_ERR_HIP if the launch's grid     */
                         /* barrier timed out before the step finished (step not completed)     */
   int32_t iters;        /* BiCGSTAB iterations (a converged half iteration counts as one)     */
-  int32_t matvecs;      /* operator applications, residual checks included                     */
+  int32_t matvecs;      /* operator applications, residual checks included (a residual check   */
+                        /* that also forms the next step's right-hand side counts once)        */
   int32_t restarts;     /* breakdown or failed true-residual restarts                          */
   int32_t outer_iters;  /* refinement steps (mixed precision), else 0                          */
-  int32_t pad_;
+  int32_t precs;        /* preconditioner solves (block LU of eq. matrixM)                     */
   double rel_res;       /* recursive residual at exit / ||b||                                  */
   double true_rel_res;  /* ||b - A x|| / ||b|| at exit                                         */
 } tdde_solve_stats;

@@ -47,7 +47,7 @@ class SolveOpts(C.Structure):
 
 class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("matvecs", C.c_int32), ("restarts", C.c_int32),
-                ("outer_iters", C.c_int32), ("pad_", C.c_int32), ("rel_res", C.c_double),
+                ("outer_iters", C.c_int32), ("precs", C.c_int32), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double)]
 
     def as_dict(self):
@@ -55,7 +55,7 @@ class SolveStats(C.Structure):
 
 
 STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"), ("restarts", "<i4"),
-                        ("outer_iters", "<i4"), ("pad_", "<i4"), ("rel_res", "<f8"), ("true_rel_res", "<f8")])
+                        ("outer_iters", "<i4"), ("precs", "<i4"), ("rel_res", "<f8"), ("true_rel_res", "<f8")])
 
 EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field", "tdde_apply",
            "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_step", "tdde_run_batched", "tdde_destroy",

@@ -35,30 +35,48 @@ struct TermLds {
   int g_live[kMaxTerms];
 };
 
-// Fill the term table (all threads call; ends with a barrier). fval(m) = f_{field_m}(t).
-template <typename T, typename F>
-__device__ inline void terms_to_lds(const DevOp<T>& op, TermLds& tl, F&& fval) {
+// Constant part of the term table: the group layout (all threads call; ends with a barrier).
+template <typename T>
+__device__ inline void terms_layout(const DevOp<T>& op, TermLds& tl) {
   __syncthreads();
   const int t = threadIdx.x;
   if (t < op.n_terms) {
-    const double f = fval(t);
-    const double2 c = op.t_coef[t];
-    tl.coef_f[t] = make_double2(c.x * f, c.y * f);
     const int m = op.g_term[t];
     tl.g_term[t] = m;
     tl.g_mask[t] = op.t_mask[m];
   }
   if (t <= op.n_groups) tl.g_first[t] = op.g_first[t];
   __syncthreads();
-  if (t < op.n_groups) {
+}
+
+// Time-dependent part: coef_f[m] = cf(m) for the calling thread's term m = threadIdx.x, and the
+// group liveness (all threads call; ends with a barrier).
+template <typename F>
+__device__ inline void terms_fields(int n_terms, int n_groups, TermLds& tl, F&& cf) {
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < n_terms) tl.coef_f[t] = cf(t);
+  __syncthreads();
+  if (t < n_groups) {
     bool any = false;
     for (int q = tl.g_first[t]; q < tl.g_first[t + 1]; ++q) {
-      const double2 cf = tl.coef_f[tl.g_term[q]];
-      any = any || cf.x != 0.0 || cf.y != 0.0;
+      const double2 c = tl.coef_f[tl.g_term[q]];
+      any = any || c.x != 0.0 || c.y != 0.0;
     }
     tl.g_live[t] = any ? 1 : 0;
   }
   __syncthreads();
+}
+
+// Whole table at once. fval(m) = f_{field_m}(t).
+template <typename T, typename F>
+__device__ inline void terms_to_lds(const DevOp<T>& op, TermLds& tl, F&& fval) {
+  terms_layout<T>(op, tl);
+  terms_fields(op.n_terms, op.n_groups, tl, [&](int m) {
+    const double f = fval(m);
+    const double2 c = op.t_coef[m];
+    return make_double2(c.x * f, c.y * f);
+  });
 }
 
 // Stage v[s'][i0-hb .. i0+kTileR+hb) of one channel into dst (zero outside [0, nr)).

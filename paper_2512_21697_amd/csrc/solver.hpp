@@ -39,7 +39,7 @@ enum { GUESS_ZERO = 0, GUESS_PREV = 1, GUESS_GIVEN = 2 };
 enum { MODE_SOLVE = 0, MODE_STEP = 1 };
 
 struct StatsDev {
-  int status, iters, matvecs, restarts, outer_iters, pad;
+  int status, iters, matvecs, restarts, outer_iters, precs;
   double rel_res, true_rel_res;
 };
 
@@ -93,7 +93,7 @@ struct WgInfo {
 };
 
 struct Inst {
-  int state, fresh, iters, matvecs, restarts, first;
+  int state, fresh, iters, matvecs, restarts, first, precs;
   int fused;       // the pending residual check also formed the next step's b, r, r^ and partials
   int nofuse;      // a failed check: form only the true residual from now on
   int next_ready;  // finished with the next step's initial data in place
@@ -262,6 +262,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       so->matvecs = st.matvecs;
       so->restarts = st.restarts;
       so->outer_iters = 0;
+      so->precs = st.precs;
       so->rel_res = st.rel_res;
       so->true_rel_res = st.true_rel_res;
     }
@@ -383,6 +384,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       if constexpr (PREC) {
         if (st.fresh) chains_own<T, MODE_FRESH>(a, wi, V, base, beta, st.omega, sh);
         else chains_own<T, MODE_P>(a, wi, V, base, beta, st.omega, sh);
+        st.precs++;
       } else {
         const c2_t<T> bc = to_c<T>(beta), oc = to_c<T>(st.omega);
         const bool fr = st.fresh;
@@ -452,6 +454,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         converged();
       } else if constexpr (PREC) {
         chains_own<T, MODE_IN_S>(a, wi, V, base, st.alpha, st.alpha, sh);  // s^ = K^-1 s
+        st.precs++;
       } else {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
         apply_own<T>(a, wi, s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
@@ -514,13 +517,32 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
   }
 }
 
-__device__ inline void fields_to_lds(const SolveArgs& a, const WgInfo& wi, double t_mid, Shared& sh,
-                                     TermLds* dst = nullptr) {
-  terms_to_lds<double>(a.op64, dst != nullptr ? *dst : sh.tl, [&](int m) {
-    if (!wi.live) return 0.0;
+// Per-thread constants of the calling thread's coupling term m = threadIdx.x for its instance:
+// prefactor, and either the pulse (time steps) or the explicit field value (single solves).
+struct TermRegs {
+  double2 coef;
+  PulseDev pulse;
+  double fval;
+};
+
+__device__ inline TermRegs term_regs(const SolveArgs& a, const WgInfo& wi) {
+  TermRegs tr{};
+  const int m = threadIdx.x;
+  if (m < a.op64.n_terms && wi.live) {
+    tr.coef = a.op64.t_coef[m];
     const int fi = a.op64.t_field[m];
-    return a.mode == MODE_STEP ? pulse_eval(a.pulses[(size_t)wi.b * a.n_fields + fi], t_mid)
-                               : a.fvals[(size_t)wi.b * a.n_fields + fi];
+    if (a.mode == MODE_STEP) tr.pulse = a.pulses[(size_t)wi.b * a.n_fields + fi];
+    else tr.fval = a.fvals[(size_t)wi.b * a.n_fields + fi];
+  }
+  return tr;
+}
+
+// Field values at t_mid into the term table (live: the instance takes part; else all zero).
+__device__ inline void fields_to_lds(const SolveArgs& a, const TermRegs& tr, bool live, double t_mid, TermLds& tl) {
+  terms_fields(a.op64.n_terms, a.op64.n_groups, tl, [&](int) {
+    if (!live) return make_double2(0.0, 0.0);
+    const double f = a.mode == MODE_STEP ? pulse_eval(tr.pulse, t_mid) : tr.fval;
+    return make_double2(tr.coef.x * f, tr.coef.y * f);
   });
 }
 
@@ -530,7 +552,7 @@ __device__ inline void fail_steps(const SolveArgs& a, const WgInfo& wi, int k) {
   for (int kk = k; kk < a.n_chunk; ++kk) {
     StatsDev& o = a.stats[(size_t)kk * a.B + wi.b];
     o.status = -2;  // TDDE_ERR_HIP
-    o.iters = o.matvecs = o.restarts = o.outer_iters = 0;
+    o.iters = o.matvecs = o.restarts = o.outer_iters = o.precs = 0;
     o.rel_res = o.true_rel_res = 0.0;
   }
 }
@@ -550,26 +572,27 @@ void persistent_kernel(SolveArgs a) {
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<double> ahc = ah, mahc = make_double2(0.0, -0.5 * a.dt);
 
+  // term tables: group layout once per launch, field values per step
+  terms_layout<double>(a.op64, sh.tl);
+  terms_layout<double>(a.op64, sh.tl2);
+  const TermRegs treg = term_regs(a, wi);
   bool ready = false;  // this step's b, x0, r, r^ and partials were formed by the previous step
   for (int k = 0; k < a.n_chunk; ++k) {
     const int step = a.step0 + k;
     int* cnt = a.counters + (size_t)k * kCounterPerStep;
-    if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
+    // the FP64 solve of the previous step ended at a grid barrier after its last write
+    if (MIXED && k > 0 && !grid_barrier(gb)) { fail_steps(a, wi, k); return; }
     mk.mark(1);
     const bool inst = wi.live && (a.mode == MODE_SOLVE || a.n_steps == nullptr || step < a.n_steps[wi.b]);
     WgInfo wk = wi;
     wk.live = inst;
     const double t_mid = a.t0 + (double)step * a.dt + 0.5 * a.dt;
-    fields_to_lds(a, wk, t_mid, sh);
+    fields_to_lds(a, treg, inst, t_mid, sh.tl);
     // the residual check of this step also forms the next step's right-hand side when the next
     // step runs in this launch for this instance
     const bool next_live = wi.live && k + 1 < a.n_chunk && (a.n_steps == nullptr || step + 1 < a.n_steps[wi.b]);
     const bool fuse = !MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN && inst && next_live;
-    if (!MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN) {
-      WgInfo wn = wi;
-      wn.live = fuse;
-      fields_to_lds(a, wn, t_mid + a.dt, sh, &sh.tl2);
-    }
+    if (!MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN) fields_to_lds(a, treg, fuse, t_mid + a.dt, sh.tl2);
     if (!inst) ready = false;
     // right-hand side buffers alternate between steps so the next one can be formed early
     double2* bbuf = (!MIXED && (k & 1)) ? a.bvec2 : a.bvec;
@@ -658,7 +681,7 @@ void persistent_kernel(SolveArgs a) {
       // ---- FP64 iterative refinement around an FP32 BiCGSTAB (inner residuals, dots in FP64)
       KVec<float> U = a.v32;
       int outer_state = inst ? ST_ACTIVE : ST_INACTIVE;
-      int total_iters = 0, total_mv = st.matvecs, outer = 0;
+      int total_iters = 0, total_mv = st.matvecs, outer = 0, total_precs = 0;
       double bb = 0.0;
       int* ocnt = cnt + 1;
       if (inst) counter_add(ocnt, 1);
@@ -710,6 +733,7 @@ void persistent_kernel(SolveArgs a) {
                             nullptr, nullptr, false);
         total_iters += ist.iters;
         total_mv += ist.matvecs;
+        total_precs += ist.precs;
         // x += ||r|| d (FP64), then r = b - A x (FP64)
         if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
         if (wq.live) {
@@ -750,6 +774,7 @@ void persistent_kernel(SolveArgs a) {
           o.matvecs = st.matvecs;
           o.restarts = 0;
           o.outer_iters = st.restarts;
+          o.precs = total_precs;
           o.rel_res = st.rel_res;
           o.true_rel_res = st.true_rel_res;
         }

@@ -809,7 +809,7 @@ static tdde_status collect_stats(tdde_ctx* c, tdde_solve_stats* out) {
     s.matvecs = h[b].matvecs;
     s.restarts = h[b].restarts;
     s.outer_iters = h[b].outer_iters;
-    s.pad_ = 0;
+    s.precs = h[b].precs;
     s.rel_res = h[b].rel_res;
     s.true_rel_res = h[b].true_rel_res;
     if (h[b].status == 2) worst = TDDE_BREAKDOWN;
