@@ -106,9 +106,9 @@ __device__ inline void stage_csr(TileLds<T>& L, const int* __restrict__ col, con
 // Stage w_k[s'][.] = sum_p val[p * K + k] * x[col[p]][s'][.] for the K terms of one pattern group and
 // the CSR row [p0, p1): every neighbouring x value is loaded once for all K terms. The CSR row is
 // read from LDS (stage_csr, after a barrier) when it fits, else from global memory; the neighbour
-// loads of kGatherBatch entries are issued together before they are used.
-constexpr int kGatherBatch = 4;
-template <typename T>
+// loads of GB entries are issued together before they are used (GB trades registers for fewer
+// dependent memory round trips).
+template <typename T, int GB>
 __device__ inline void stage_gather(TileLds<T>& L, const c2_t<T>* __restrict__ xinst, const int* __restrict__ col,
                                     const T* __restrict__ val, int p0, int p1, int K, int i0, int nr) {
   constexpr int hb = kHB;
@@ -123,16 +123,16 @@ __device__ inline void stage_gather(TileLds<T>& L, const c2_t<T>* __restrict__ x
     c2_t<T> acc[kMaxGroup];
 #pragma unroll
     for (int q = 0; q < kMaxGroup; ++q) acc[q] = cmk<T>(0, 0);
-    for (int pb = 0; pb < n; pb += kGatherBatch) {
-      c2_t<T> xv[kGatherBatch];
+    for (int pb = 0; pb < n; pb += GB) {
+      c2_t<T> xv[GB];
 #pragma unroll
-      for (int u = 0; u < kGatherBatch; ++u) {
+      for (int u = 0; u < GB; ++u) {
         const int p = pb + u < n ? pb + u : n - 1;
         const int c = in_lds ? L.gcol[p] : col[p0 + p];
         xv[u] = xinst[(size_t)c * cstride + (size_t)s * nr + gic];
       }
 #pragma unroll
-      for (int u = 0; u < kGatherBatch; ++u) {
+      for (int u = 0; u < GB; ++u) {
         if (pb + u < n) {
           const T* v = (in_lds ? L.gval : val) + (size_t)(pb + u) * K;
 #pragma unroll
@@ -185,7 +185,7 @@ __device__ inline c2_t<T> ccontract(const CTaps<T>& t, const c2_t<T>* x, c2_t<T>
 // branches around loads depend only on the spinor component s, which is uniform over a wave
 // (128 threads per component), so they are scalar branches: H0/S taps are loaded before the
 // staging barrier is passed, coupling bands two terms at a time.
-template <typename T, bool TWO = false>
+template <typename T, bool TWO = false, int GB = 4>
 __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict__ xinst, int j, int i0,
                                    const TermLds& tl, TileLds<T>& L, const TermLds* tl2 = nullptr) {
   constexpr int hb = kHB, nb = 2 * kHB + 1;
@@ -216,7 +216,7 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
   if (g0 && g0_p0 != g0_p1) {
     stage_csr<T>(L, op.g_col, g0_val, g0_p0, g0_p1, g0_K);
     __syncthreads();
-    stage_gather<T>(L, xinst, op.g_col, g0_val, g0_p0, g0_p1, g0_K, i0, nr);
+    stage_gather<T, GB>(L, xinst, op.g_col, g0_val, g0_p0, g0_p1, g0_K, i0, nr);
   }
 
   // ---- H0 / S / channel taps of this kappa block: the real tap blocks this thread needs are listed
@@ -288,7 +288,7 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
       __syncthreads();
       stage_csr<T>(L, op.g_col, gv, p0, p1, K);
       __syncthreads();
-      stage_gather<T>(L, xinst, op.g_col, gv, p0, p1, K, i0, nr);
+      stage_gather<T, GB>(L, xinst, op.g_col, gv, p0, p1, K, i0, nr);
       __syncthreads();
     }
 #pragma unroll

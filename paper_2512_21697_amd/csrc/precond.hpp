@@ -70,7 +70,7 @@ template <typename T> struct ChainIO {
 // loaded before the current row is computed and its results stored, so the loads overlap the
 // arithmetic of the rows before them instead of one memory latency being paid per row.
 #ifndef TDDE_CHAIN_AHEAD
-#define TDDE_CHAIN_AHEAD 2
+#define TDDE_CHAIN_AHEAD 1
 #endif
 constexpr int kChainAhead = TDDE_CHAIN_AHEAD;
 

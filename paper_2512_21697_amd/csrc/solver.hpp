@@ -143,7 +143,7 @@ template <typename T> __device__ inline SharedLds<T>& lds_of(Shared& sh);
 template <> __device__ inline SharedLds<double>& lds_of<double>(Shared& sh) { return sh.u.d; }
 template <> __device__ inline SharedLds<float>& lds_of<float>(Shared& sh) { return sh.u.f; }
 
-// Tile loop of the calling work-group over its instance.
+// Tile loop of the calling work-group over its instance (radial tile fastest).
 #define FOR_TILES(op, wi)                                                          \
   for (int tile_ = (wi).g; tile_ < (op).nang * (op).n_itiles; tile_ += (wi).G)     \
     for (int j_ = tile_ / (op).n_itiles, once_ = 1; once_; once_ = 0)             \
@@ -163,22 +163,23 @@ __device__ inline c2_t<T> load_c(const c2_t<T>* p, long e) { return p[e]; }
 
 // y = S x + ah * H x for own tiles of instance b (A of the step), with optional fused outputs.
 // The caller supplies a functor on (element, S x, H x).
-template <typename T, typename F>
+// GB: neighbour loads of a gather issued together (more registers, fewer round trips).
+template <typename T, int GB = 4, typename F>
 __device__ inline void apply_own(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
   const DevOp<T>& op = op_of<T>(a);
   FOR_TILES(op, wi) {
-    SH<T> r = apply_tile<T>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile);
+    SH<T> r = apply_tile<T, false, GB>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile);
     const long e = tile_elem<T>(op, j_, i0_);
     if (e >= 0) f(e, r.sx, r.hx);
   }
 }
 
 // Same with the next step's fields as well: f(e, S x, H x, H_next x).
-template <typename T, typename F>
+template <typename T, int GB = 4, typename F>
 __device__ inline void apply_own2(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
   const DevOp<T>& op = op_of<T>(a);
   FOR_TILES(op, wi) {
-    SH<T> r = apply_tile<T, true>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile, &sh.tl2);
+    SH<T> r = apply_tile<T, true, GB>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile, &sh.tl2);
     const long e = tile_elem<T>(op, j_, i0_);
     if (e >= 0) f(e, r.sx, r.hx, r.hx2);
   }
@@ -235,6 +236,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<T> ahc = to_c<T>(ah);
   constexpr bool prec = PREC;
+  constexpr int kGB = 4;
   c2_t<T>* x = V.x + base;
   c2_t<T>* r = V.r + base;
   c2_t<T>* rh = V.rh + base;
@@ -286,7 +288,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         double2 acc = make_double2(0.0, 0.0), accb = make_double2(0.0, 0.0), accr = make_double2(0.0, 0.0);
         const c2_t<T> mahc = cmk<T>(-ahc.x, -ahc.y), mdt = cmk<T>(0, (T)(-a.dt));
         const bool prev = a.guess == GUESS_PREV;
-        apply_own2<T>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx, c2_t<T> hx2) {
+        apply_own2<T, kGB>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx, c2_t<T> hx2) {
           const c2_t<T> rt = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
           dot_acc(acc, rt, rt);
           const c2_t<T> bn = cfma<T>(mahc, hx2, sx);
@@ -304,7 +306,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         st.fused = 1;
       } else {
         double2 acc = make_double2(0.0, 0.0);
-        apply_own<T>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        apply_own<T, kGB>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
           const c2_t<T> rr = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
           r[e] = rr;
           dot_acc(acc, rr, rr);
@@ -402,7 +404,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     s0 = wi.live ? st.state : ST_INACTIVE;
     if (s0 == ST_ACTIVE) {
       double2 acc = make_double2(0.0, 0.0);
-      apply_own<T>(a, wi, prec ? ph : p, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+      apply_own<T, kGB>(a, wi, prec ? ph : p, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
         const c2_t<T> vv = cfma<T>(ahc, hx, sx);
         v[e] = vv;
         dot_acc(acc, rh[e], vv);
@@ -457,7 +459,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         st.precs++;
       } else {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
-        apply_own<T>(a, wi, s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        apply_own<T, kGB>(a, wi, s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
           const c2_t<T> tv = cfma<T>(ahc, hx, sx);
           t[e] = tv;
           dot_acc(ts, tv, s[e]);
@@ -477,7 +479,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       s0 = wi.live ? st.state : ST_INACTIVE;
       if (s0 == ST_ACTIVE) {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
-        apply_own<T>(a, wi, shv, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        apply_own<T, kGB>(a, wi, shv, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
           const c2_t<T> tv = cfma<T>(ahc, hx, sx);
           t[e] = tv;
           dot_acc(ts, tv, s[e]);
