@@ -185,7 +185,8 @@ __device__ inline c2_t<T> ccontract(const CTaps<T>& t, const c2_t<T>* x, c2_t<T>
 // branches around loads depend only on the spinor component s, which is uniform over a wave
 // (128 threads per component), so they are scalar branches: H0/S taps are loaded before the
 // staging barrier is passed, coupling bands two terms at a time.
-template <typename T, bool TWO = false, int GB = 4>
+// GB: gather batch; TR: coupling terms whose bands are loaded together (registers vs round trips).
+template <typename T, bool TWO = false, int GB = 4, int TR = 2>
 __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict__ xinst, int j, int i0,
                                    const TermLds& tl, TileLds<T>& L, const TermLds* tl2 = nullptr) {
   constexpr int hb = kHB, nb = 2 * kHB + 1;
@@ -275,7 +276,7 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
   if (TWO) out.hx2 = out.hx;
 
   // ---- coupling terms: stage the angular combinations of a pattern group, then the band
-  // contractions, the bands of two terms loaded together
+  // contractions, the bands of TR terms loaded together
   for (int gidx = 0; gidx < op.n_groups; ++gidx) {
     if (!live_g(gidx)) continue;  // uniform over the work-group
     const int f0 = tl.g_first[gidx], K = tl.g_first[gidx + 1] - f0;
@@ -292,12 +293,12 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
       __syncthreads();
     }
 #pragma unroll
-    for (int q0 = 0; q0 < kMaxGroup; q0 += 2) {
+    for (int q0 = 0; q0 < kMaxGroup; q0 += TR) {
       if (q0 < K) {
-        Taps<T> tr[2][2];
-        int mask[2], m[2];
+        Taps<T> tr[TR][2];
+        int mask[TR], m[TR];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < TR; ++h) {
           const int q = q0 + h;
           m[h] = q < K ? tl.g_term[f0 + q] : 0;
           mask[h] = q < K ? (tl.g_mask[f0 + q] >> (2 * s)) & 3 : 0;
@@ -307,7 +308,7 @@ __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict
               load_taps<T>(tr[h][s2], op.t_r + ((size_t)m[h] * 4 + s * 2 + s2) * bstride + ic, nr);
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < TR; ++h) {
           if (q0 + h < K) {
             c2_t<T> acc = cmk<T>(0, 0);
 #pragma unroll

@@ -120,6 +120,22 @@ __device__ inline void put_partial(const SolveArgs& a, const WgInfo& wi, int slo
   const double2 s = wg_sum2(v, sh.red);
   if (threadIdx.x == 0) a.part[((size_t)wi.b * wi.G + wi.g) * kSlots + slot] = s;
 }
+// Three slots at once (one round of partial loads).
+__device__ inline void get_totals3(const SolveArgs& a, const WgInfo& wi, int s0, int s1, int s2, double2& t0,
+                                   double2& t1, double2& t2, Shared& sh) {
+  double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0;
+  for (int gg = threadIdx.x; gg < wi.G; gg += kThreads) {
+    const double2* p = a.part + ((size_t)wi.b * wi.G + gg) * kSlots;
+    const double2 v0 = p[s0], v1 = p[s1], v2 = p[s2];
+    a0.x += v0.x; a0.y += v0.y;
+    a1.x += v1.x; a1.y += v1.y;
+    a2.x += v2.x; a2.y += v2.y;
+  }
+  t0 = wg_sum2(a0, sh.red);
+  t1 = wg_sum2(a1, sh.red);
+  t2 = wg_sum2(a2, sh.red);
+}
+
 __device__ inline double2 get_total(const SolveArgs& a, const WgInfo& wi, int slot, Shared& sh) {
   double2 acc = make_double2(0.0, 0.0);
   for (int gg = threadIdx.x; gg < wi.G; gg += kThreads) {
@@ -164,22 +180,22 @@ __device__ inline c2_t<T> load_c(const c2_t<T>* p, long e) { return p[e]; }
 // y = S x + ah * H x for own tiles of instance b (A of the step), with optional fused outputs.
 // The caller supplies a functor on (element, S x, H x).
 // GB: neighbour loads of a gather issued together (more registers, fewer round trips).
-template <typename T, int GB = 4, typename F>
+template <typename T, int GB = 4, int TR = 2, typename F>
 __device__ inline void apply_own(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
   const DevOp<T>& op = op_of<T>(a);
   FOR_TILES(op, wi) {
-    SH<T> r = apply_tile<T, false, GB>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile);
+    SH<T> r = apply_tile<T, false, GB, TR>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile);
     const long e = tile_elem<T>(op, j_, i0_);
     if (e >= 0) f(e, r.sx, r.hx);
   }
 }
 
 // Same with the next step's fields as well: f(e, S x, H x, H_next x).
-template <typename T, int GB = 4, typename F>
+template <typename T, int GB = 4, int TR = 2, typename F>
 __device__ inline void apply_own2(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
   const DevOp<T>& op = op_of<T>(a);
   FOR_TILES(op, wi) {
-    SH<T> r = apply_tile<T, true, GB>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile, &sh.tl2);
+    SH<T> r = apply_tile<T, true, GB, TR>(op, xin, j_, i0_, sh.tl, lds_of<T>(sh).tile, &sh.tl2);
     const long e = tile_elem<T>(op, j_, i0_);
     if (e >= 0) f(e, r.sx, r.hx, r.hx2);
   }
@@ -237,6 +253,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
   const c2_t<T> ahc = to_c<T>(ah);
   constexpr bool prec = PREC;
   constexpr int kGB = 4;
+  constexpr int kTR = PREC ? 4 : 2;  // the preconditioned variant has 512 registers per lane
   c2_t<T>* x = V.x + base;
   c2_t<T>* r = V.r + base;
   c2_t<T>* rh = V.rh + base;
@@ -288,7 +305,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         double2 acc = make_double2(0.0, 0.0), accb = make_double2(0.0, 0.0), accr = make_double2(0.0, 0.0);
         const c2_t<T> mahc = cmk<T>(-ahc.x, -ahc.y), mdt = cmk<T>(0, (T)(-a.dt));
         const bool prev = a.guess == GUESS_PREV;
-        apply_own2<T, kGB>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx, c2_t<T> hx2) {
+        apply_own2<T, kGB, kTR>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx, c2_t<T> hx2) {
           const c2_t<T> rt = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
           dot_acc(acc, rt, rt);
           const c2_t<T> bn = cfma<T>(mahc, hx2, sx);
@@ -306,7 +323,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         st.fused = 1;
       } else {
         double2 acc = make_double2(0.0, 0.0);
-        apply_own<T, kGB>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        apply_own<T, kGB, kTR>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
           const c2_t<T> rr = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
           r[e] = rr;
           dot_acc(acc, rr, rr);
@@ -348,10 +365,12 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     if (s0 == ST_ACTIVE || s0 == ST_PENDING) {
       const bool pend = s0 == ST_PENDING;
       const bool nx = st.first && from_next;  // initial partials formed by the previous step
-      const double2 rho = get_total(a, wi, pend ? SLOT_AUX : (nx ? SLOT_NRHO : SLOT_RHO), sh);
-      const double rr = pend ? rho.x : get_total(a, wi, nx ? SLOT_NRR : SLOT_RR, sh).x;
+      double2 rho, rrt, bbt;
+      get_totals3(a, wi, pend ? SLOT_AUX : (nx ? SLOT_NRHO : SLOT_RHO), nx ? SLOT_NRR : SLOT_RR,
+                  nx ? SLOT_NBB : SLOT_BB, rho, rrt, bbt, sh);
+      const double rr = pend ? rho.x : rrt.x;
       if (st.first) {
-        st.bb = get_total(a, wi, nx ? SLOT_NBB : SLOT_BB, sh).x;
+        st.bb = bbt.x;
         st.target2 = tol * tol * st.bb;
         st.first = 0;
       }
@@ -404,7 +423,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     s0 = wi.live ? st.state : ST_INACTIVE;
     if (s0 == ST_ACTIVE) {
       double2 acc = make_double2(0.0, 0.0);
-      apply_own<T, kGB>(a, wi, prec ? ph : p, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+      apply_own<T, kGB, kTR>(a, wi, prec ? ph : p, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
         const c2_t<T> vv = cfma<T>(ahc, hx, sx);
         v[e] = vv;
         dot_acc(acc, rh[e], vv);
@@ -459,7 +478,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         st.precs++;
       } else {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
-        apply_own<T, kGB>(a, wi, s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        apply_own<T, kGB, kTR>(a, wi, s, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
           const c2_t<T> tv = cfma<T>(ahc, hx, sx);
           t[e] = tv;
           dot_acc(ts, tv, s[e]);
@@ -479,7 +498,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       s0 = wi.live ? st.state : ST_INACTIVE;
       if (s0 == ST_ACTIVE) {
         double2 ts = make_double2(0.0, 0.0), tt = make_double2(0.0, 0.0);
-        apply_own<T, kGB>(a, wi, shv, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
+        apply_own<T, kGB, kTR>(a, wi, shv, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
           const c2_t<T> tv = cfma<T>(ahc, hx, sx);
           t[e] = tv;
           dot_acc(ts, tv, s[e]);
@@ -497,8 +516,9 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     mk.mark(14);
     s0 = wi.live ? st.state : ST_INACTIVE;
     if (s0 == ST_ACTIVE) {
-      const double2 ts = get_total(a, wi, SLOT_TS, sh);
-      const double tt = get_total(a, wi, SLOT_TT, sh).x;
+      double2 ts, ttt, unused;
+      get_totals3(a, wi, SLOT_TS, SLOT_TT, SLOT_TT, ts, ttt, unused, sh);
+      const double tt = ttt.x;
       st.omega = tt > 0.0 ? make_double2(ts.x / tt, ts.y / tt) : make_double2(0.0, 0.0);
       const c2_t<T> al = to_c<T>(st.alpha), om = to_c<T>(st.omega);
       const c2_t<T>* pd = prec ? ph : p;
@@ -618,7 +638,7 @@ void persistent_kernel(SolveArgs a) {
         const double2* psi = a.psi + base;
         const int gs = a.guess;
         const bool direct_r = !MIXED && gs != GUESS_GIVEN;
-        apply_own<double>(a, wk, psi, sh, [&](long e, double2 sx, double2 hx) {
+        apply_own<double, 4, PREC ? 4 : 2>(a, wk, psi, sh, [&](long e, double2 sx, double2 hx) {
           const double2 bval = cfma<double>(mahc, hx, sx);
           bv[e] = bval;
           dot_acc(bb, bval, bval);
@@ -655,7 +675,7 @@ void persistent_kernel(SolveArgs a) {
       if (inst) {
         double2 rr = {0, 0};
         double2* rt = MIXED ? a.r64 + base : V.r + base;
-        apply_own<double>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
+        apply_own<double, 4, PREC ? 4 : 2>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
           const double2 rv = csub<double>(bv[e], cfma<double>(ahc, hx, sx));
           rt[e] = rv;
           if (!MIXED) V.rh[base + e] = rv;
@@ -749,7 +769,7 @@ void persistent_kernel(SolveArgs a) {
         if (wq.live) {
           double2 rr = {0, 0};
           double2* rt = a.r64 + base;
-          apply_own<double>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
+          apply_own<double, 4, PREC ? 4 : 2>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
             const double2 rv = csub<double>(bv[e], cfma<double>(ahc, hx, sx));
             rt[e] = rv;
             dot_acc(rr, rv, rv);
