@@ -39,6 +39,31 @@ template <typename T> __device__ inline c2_t<T> rfma(T r, c2_t<T> b, c2_t<T> acc
 }
 template <typename T> __device__ inline c2_t<T> cscale(T r, c2_t<T> b) { return cmk<T>(r * b.x, r * b.y); }
 
+// Loads and stores of device (global) memory through address-space-1 pointers. A pointer that
+// reaches an outlined function is generic, and generic (flat) accesses share one wait counter with
+// LDS accesses.
+#define TDDE_GLOBAL __attribute__((address_space(1)))
+typedef double gvd2 __attribute__((ext_vector_type(2)));
+typedef float gvf2 __attribute__((ext_vector_type(2)));
+__device__ __attribute__((always_inline)) inline double2 gld(const double2* p) {
+  const gvd2 v = *(const TDDE_GLOBAL gvd2*)p;
+  return make_double2(v.x, v.y);
+}
+__device__ __attribute__((always_inline)) inline float2 gld(const float2* p) {
+  const gvf2 v = *(const TDDE_GLOBAL gvf2*)p;
+  return make_float2(v.x, v.y);
+}
+__device__ __attribute__((always_inline)) inline void gst(double2* p, double2 x) {
+  gvd2 v;
+  v.x = x.x; v.y = x.y;
+  *(TDDE_GLOBAL gvd2*)p = v;
+}
+__device__ __attribute__((always_inline)) inline void gst(float2* p, float2 x) {
+  gvf2 v;
+  v.x = x.x; v.y = x.y;
+  *(TDDE_GLOBAL gvf2*)p = v;
+}
+
 // conj(a) * b accumulated in double
 __device__ inline void dot_acc(double2& acc, double2 a, double2 b) {
   acc.x = fma(a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);

@@ -90,16 +90,16 @@ __device__ inline void row_fetch(RowOps<T, NC>& ro, const c2_t<T>* LU, const Cha
   const size_t e = prow(q, nr);
   const c2_t<T>* row = LU + ((size_t)t * kPrecStride + (KIND <= SUB_L3 ? 0 : kPrecW)) * P;
 #pragma unroll
-  for (int k = 0; k < NC; ++k) ro.c[k] = row[(size_t)k * P];
+  for (int k = 0; k < NC; ++k) ro.c[k] = gld(row + (size_t)k * P);
   if (KIND == SUB_L1) {
-    if constexpr (MODE == MODE_P) { ro.z0 = io.r[e]; ro.z1 = io.pz[e]; ro.z2 = io.v[e]; }
-    else if constexpr (MODE == MODE_S) { ro.z0 = io.r[e]; ro.z2 = io.v[e]; }
-    else if constexpr (MODE == MODE_FRESH) { ro.z0 = io.r[e]; }
-    else { ro.z0 = io.pz[e]; }
+    if constexpr (MODE == MODE_P) { ro.z0 = gld(io.r + e); ro.z1 = gld(io.pz + e); ro.z2 = gld(io.v + e); }
+    else if constexpr (MODE == MODE_S) { ro.z0 = gld(io.r + e); ro.z2 = gld(io.v + e); }
+    else if constexpr (MODE == MODE_FRESH) { ro.z0 = gld(io.r + e); }
+    else { ro.z0 = gld(io.pz + e); }
   } else if (KIND == SUB_L3) {
-    ro.z0 = io.pz[e];  // the input formed (and stored) in phase 1
+    ro.z0 = gld(io.pz + e);  // the input formed (and stored) in phase 1
   } else {
-    ro.z0 = io.out[e];  // y of the lower solve (U1), or y overwritten by nothing yet (U3)
+    ro.z0 = gld(io.out + e);  // y of the lower solve (U1), or y overwritten by nothing yet (U3)
   }
 }
 
@@ -165,8 +165,8 @@ __device__ inline void substitute(const c2_t<T>* LU, int P, const ChainIO<T>& io
           const int tt = lower ? t + D : len - 1 - t - D;
           row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, o + tt, tt, P);
         }
-        if (KIND == SUB_L1 && MODE != MODE_IN && MODE != MODE_IN_S) io.pz[e] = zin;
-        if (KIND == SUB_L3 || KIND == SUB_U3) io.out[e] = acc;
+        if (KIND == SUB_L1 && MODE != MODE_IN && MODE != MODE_IN_S) gst(io.pz + e, zin);
+        if (KIND == SUB_L3 || KIND == SUB_U3) gst(io.out + e, acc);
       }
     }
   }
@@ -197,7 +197,7 @@ __device__ inline void group_recurrence(const c2_t<T>* Tm, int P, ChainLds<T>& L
     const int p = LOWER ? lo + step : hi - step;
     if (act && step < kSegGroup && (LOWER ? p <= hi : p >= lo)) {
 #pragma unroll
-      for (int c = 0; c < W; ++c) tr[c] = Tm[((size_t)p * W + c) * W + r];
+      for (int c = 0; c < W; ++c) tr[c] = gld(Tm + ((size_t)p * W + c) * W + r);
     }
   };
   fetch(1);
@@ -235,7 +235,7 @@ __device__ inline void group_boundaries(const c2_t<T>* Cm, int P, ChainLds<T>& L
     if (G >= 0 && G < NG && G != G0) {
       const int p = seg_of(G);
 #pragma unroll
-      for (int c = 0; c < W; ++c) cr[c] = Cm[((size_t)r * W + c) * cs + p];
+      for (int c = 0; c < W; ++c) cr[c] = gld(Cm + ((size_t)r * W + c) * cs + p);
     }
   };
   fetch(LOWER ? 1 : NG - 2);
@@ -271,7 +271,7 @@ __device__ inline void true_window(const c2_t<T>* Cm, int P, int q, const ChainL
     for (int rr = 0; rr < W; ++rr) {
       c2_t<T> acc = out[rr];
 #pragma unroll
-      for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(Cm[((size_t)rr * W + c) * P + q], uu[c]));
+      for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(gld(Cm + ((size_t)rr * W + c) * P + q), uu[c]));
       out[rr] = acc;
     }
   }

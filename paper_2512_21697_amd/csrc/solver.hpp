@@ -244,11 +244,15 @@ __device__ inline void chains_own(const SolveArgs& a, const WgInfo& wi, const KV
 // unfinished-work-group counter *cnt already counts this work-group. verify: confirm convergence
 // with the true residual (restart on failure). On its final transition an instance writes its
 // iterate to dst (when not null) and its statistics to *so (when not null). The loop ends at the
-// first barrier after which no work-group of the launch is unfinished.
+// first barrier after which no work-group of the launch is unfinished. need_init (when not null):
+// counter of instances whose next step in the launch must form its own initial data, incremented
+// on the final transition. skip_first: the caller has just passed a grid barrier after which every
+// input of the first window is in place (the first window then starts without one).
 template <typename T, bool PREC>
 __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, const c2_t<T>* rhs, size_t base,
                               double tol, int max_iter, bool verify, int* cnt, Inst& st, Shared& sh, Marks& mk,
-                              GridBar& gb, c2_t<T>* dst, StatsDev* so, c2_t<T>* bnext_buf, bool from_next) {
+                              GridBar& gb, c2_t<T>* dst, StatsDev* so, c2_t<T>* bnext_buf, bool from_next,
+                              int* need_init = nullptr, bool skip_first = false) {
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<T> ahc = to_c<T>(ah);
   constexpr bool prec = PREC;
@@ -275,6 +279,8 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         if (dst != nullptr) dst[e] = x[e];
         if (zero_x) x[e] = cmk<T>(0, 0);
       });
+    if (need_init != nullptr && !st.next_ready && wi.g == 0 && threadIdx.x == 0)
+      __hip_atomic_fetch_add(need_init, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (so != nullptr && wi.g == 0 && threadIdx.x == 0) {
       so->status = state == ST_DONE ? 0 : (state == ST_BREAKDOWN ? 2 : 1);
       so->iters = st.iters;
@@ -356,8 +362,11 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
   while (true) {
     int left = 0;  // work-groups of the launch still unfinished after the barrier
     // ---------------- W0
-    if (!grid_barrier(gb, cnt, &left)) return;
-    if (left == 0) break;
+    if (!skip_first) {
+      if (!grid_barrier(gb, cnt, &left)) return;
+      if (left == 0) break;
+    }
+    skip_first = false;
     mk.mark(10);
     int s0 = wi.live ? st.state : ST_INACTIVE;
     bool work = false;
@@ -695,8 +704,18 @@ void persistent_kernel(SolveArgs a) {
       if (inst) counter_add(cnt, 1);
       double2* dst = (a.mode == MODE_STEP ? a.psi : a.x_io) + base;
       StatsDev* so = a.stats != nullptr ? a.stats + (size_t)k * a.B + wk.b : nullptr;
+      // Steps after the first: the previous step's solve ended at a grid barrier, and when no
+      // instance has to form its own initial data (count of the previous step's final transitions
+      // without the next step's data in place, complete at that barrier) nothing has been written
+      // since, so the first window needs no barrier of its own. The count is the same in every
+      // work-group, so every work-group makes the same choice.
+      const bool chained = a.mode == MODE_STEP && a.guess != GUESS_GIVEN;
+      const bool skip = chained && k > 0 &&
+                        __hip_atomic_load(a.counters + (size_t)k * kCounterPerStep + 1, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) == 0;
+      int* need_next = chained && k + 1 < a.n_chunk ? a.counters + (size_t)(k + 1) * kCounterPerStep + 1 : nullptr;
       krylov<double, PREC>(a, wk, V, bbuf, base, a.tol, a.max_iter, true, cnt, st, sh, mk, gb, dst, so,
-                           fuse ? bnbuf : nullptr, ready);
+                           fuse ? bnbuf : nullptr, ready, need_next, skip);
       ready = inst && st.next_ready;
       if (gb.failed) { fail_steps(a, wi, k); return; }
     } else {
