@@ -649,11 +649,11 @@ tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
   const int nr = c->d.nr, hb = c->d.half_band, n = 2 * nr, w = 2 * hb + 1, ws = 2 * w + 1;
   if (w != kPrecW) return TDDE_OK;  // preconditioner available for half_band 6 only (checked at solve)
   if (n < w) return TDDE_OK;
-  // Segments of at least 32 rows: half the segment-boundary matrices (T, C) of 16-row segments, so
-  // more of the factors stay resident in the Infinity Cache beside the solver's vectors between two
-  // solves (hydrogen: 129 MB instead of 186 MB); a solve alone is slower (longer substitutions per
-  // thread), a solve inside the time step faster.
-  const int m = std::max({w, 32, (n + kMaxSeg - 1) / kMaxSeg});
+  // Segments of at least 24 rows: two thirds of the segment-boundary matrices (T, C) of 16-row
+  // segments, so more of the factors stay resident in the Infinity Cache beside the solver's vectors
+  // between two solves (hydrogen: 147 MB instead of 186 MB). Measured on the hydrogen step, 24 rows
+  // beat 16, 32, 40 and 48 (longer segments lengthen each thread's substitution chain).
+  const int m = std::max({w, 24, (n + kMaxSeg - 1) / kMaxSeg});
   const int P = (n + m - 1) / m;
   std::vector<cd> LU, TL, TU, CL, CU;
   const size_t tsz = (size_t)P * w * w;
