@@ -56,6 +56,7 @@ struct SolveArgs {
   KVec<float> v32;
   double2* bvec;          // right-hand side workspace (FP64), even steps of a launch
   double2* bvec2;         // right-hand side of odd steps (the next step's is formed during this one)
+  double2* xalt;          // second iterate buffer: x + alpha p^ formed with s, ahead of the half-step test
   double2* r64;           // outer residual (mixed precision)
   float2* rhs32;          // inner right-hand side (mixed precision)
   int B, G, E, n_wg;
@@ -97,6 +98,9 @@ struct Inst {
   int fused;       // the pending residual check also formed the next step's b, r, r^ and partials
   int nofuse;      // a failed check: form only the true residual from now on
   int next_ready;  // finished with the next step's initial data in place
+  int xsel;        // the iterate lives in the second buffer
+  int xahead;      // the other buffer holds x + alpha p^ of this iteration
+  int spec_it;     // iteration whose half step is expected to end the solve (x + alpha p^ formed ahead)
   double2 rho, alpha, omega;
   double bb, target2, rel_res, true_rel_res;
 };
@@ -252,13 +256,16 @@ template <typename T, bool PREC>
 __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, const c2_t<T>* rhs, size_t base,
                               double tol, int max_iter, bool verify, int* cnt, Inst& st, Shared& sh, Marks& mk,
                               GridBar& gb, c2_t<T>* dst, StatsDev* so, c2_t<T>* bnext_buf, bool from_next,
-                              int* need_init = nullptr, bool skip_first = false) {
+                              int* need_init = nullptr, bool skip_first = false, c2_t<T>* xalt_buf = nullptr) {
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<T> ahc = to_c<T>(ah);
   constexpr bool prec = PREC;
   constexpr int kGB = 4;
   constexpr int kTR = PREC ? 4 : 2;  // the preconditioned variant has 512 registers per lane
-  c2_t<T>* x = V.x + base;
+  // the iterate and the other iterate buffer (xalt_buf: x + alpha p^ is formed there with s when the
+  // half step may end the solve, and the two buffers swap roles when it does)
+  c2_t<T>* x = (st.xsel ? xalt_buf : V.x) + base;
+  c2_t<T>* xo = xalt_buf != nullptr ? (st.xsel ? V.x : xalt_buf) + base : nullptr;
   c2_t<T>* r = V.r + base;
   c2_t<T>* rh = V.rh + base;
   c2_t<T>* p = V.p + base;
@@ -302,31 +309,34 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       finish(ST_DONE);
     }
   };
+  // true residual of this step (its norm) together with the next step's right-hand side
+  // b' = (S - i dt/2 H') x, residual r' = b' - A' x0 and r^' = r' (H': next step's fields)
+  auto fused_check = [&]() {
+    double2 acc = make_double2(0.0, 0.0), accb = make_double2(0.0, 0.0), accr = make_double2(0.0, 0.0);
+    const c2_t<T> mahc = cmk<T>(-ahc.x, -ahc.y), mdt = cmk<T>(0, (T)(-a.dt));
+    const bool prev = a.guess == GUESS_PREV;
+    apply_own2<T, kGB, kTR>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx, c2_t<T> hx2) {
+      const c2_t<T> rt = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
+      dot_acc(acc, rt, rt);
+      const c2_t<T> bn = cfma<T>(mahc, hx2, sx);
+      bnext[e] = bn;
+      dot_acc(accb, bn, bn);
+      const c2_t<T> rn = prev ? cmul<T>(mdt, hx2) : bn;  // x0 = x: b' - A' x = -i dt H' x
+      r[e] = rn;
+      rh[e] = rn;
+      dot_acc(accr, rn, rn);
+    });
+    put_partial(a, wi, SLOT_RR, acc, sh);
+    put_partial(a, wi, SLOT_NBB, accb, sh);
+    put_partial(a, wi, SLOT_NRHO, accr, sh);
+    put_partial(a, wi, SLOT_NRR, accr, sh);
+    st.fused = 1;
+  };
   // true-residual states, handled in whichever window comes next (s0: state at window entry)
   auto verify_step = [&](int s0) {
     if (s0 == ST_VERIFY) {
       if (bnext != nullptr && !st.nofuse) {
-        // true residual of this step (its norm) together with the next step's right-hand side
-        // b' = (S - i dt/2 H') x, residual r' = b' - A' x0 and r^' = r' (H': next step's fields)
-        double2 acc = make_double2(0.0, 0.0), accb = make_double2(0.0, 0.0), accr = make_double2(0.0, 0.0);
-        const c2_t<T> mahc = cmk<T>(-ahc.x, -ahc.y), mdt = cmk<T>(0, (T)(-a.dt));
-        const bool prev = a.guess == GUESS_PREV;
-        apply_own2<T, kGB, kTR>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx, c2_t<T> hx2) {
-          const c2_t<T> rt = csub<T>(b_[e], cfma<T>(ahc, hx, sx));
-          dot_acc(acc, rt, rt);
-          const c2_t<T> bn = cfma<T>(mahc, hx2, sx);
-          bnext[e] = bn;
-          dot_acc(accb, bn, bn);
-          const c2_t<T> rn = prev ? cmul<T>(mdt, hx2) : bn;  // x0 = x: b' - A' x = -i dt H' x
-          r[e] = rn;
-          rh[e] = rn;
-          dot_acc(accr, rn, rn);
-        });
-        put_partial(a, wi, SLOT_RR, acc, sh);
-        put_partial(a, wi, SLOT_NBB, accb, sh);
-        put_partial(a, wi, SLOT_NRHO, accr, sh);
-        put_partial(a, wi, SLOT_NRR, accr, sh);
-        st.fused = 1;
+        fused_check();
       } else {
         double2 acc = make_double2(0.0, 0.0);
         apply_own<T, kGB, kTR>(a, wi, x, sh, [&](long e, c2_t<T> sx, c2_t<T> hx) {
@@ -456,14 +466,21 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
         put_partial(a, wi, SLOT_AUX, acc, sh);
       } else {
         st.alpha = cdiv(st.rho, rv);
-        // the preconditioned s^ is formed only if the half step does not already converge (W3)
+        // the preconditioned s^ is formed only if the half step does not already converge (W3);
+        // in the iteration whose half step ended the previous step's solve, when the residual
+        // check would also form the next step's data, x + alpha p^ is formed here too, so that the
+        // check can run in the window of the test
         double n2 = 0.0;
         const c2_t<T> al = to_c<T>(st.alpha);
+        const c2_t<T>* dir = prec ? ph : p;
+        const bool ahead = xo != nullptr && verify && bnext != nullptr && !st.nofuse && st.iters == st.spec_it;
         elem_own<T>(a, wi, [&](long e) {
           const c2_t<T> sv = csub<T>(r[e], cmul<T>(al, v[e]));
           s[e] = sv;
           n2 += (double)sv.x * sv.x + (double)sv.y * sv.y;
+          if (ahead) xo[e] = cfma<T>(al, dir[e], x[e]);
         });
+        st.xahead = ahead;
         put_partial(a, wi, SLOT_SS, make_double2(n2, 0.0), sh);
       }
     }
@@ -476,12 +493,24 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     if (s0 == ST_ACTIVE) {
       const double ss = get_total(a, wi, SLOT_SS, sh).x;
       if (ss <= st.target2) {
-        const c2_t<T> al = to_c<T>(st.alpha);
-        const c2_t<T>* dir = prec ? ph : p;
-        elem_own<T>(a, wi, [&](long e) { x[e] = cfma<T>(al, dir[e], x[e]); });
         st.iters++;
         st.rel_res = st.bb > 0 ? sqrt(ss / st.bb) : 0.0;
-        converged();
+        if (st.xahead) {
+          // x + alpha p^ is in the other buffer: it becomes the iterate, and its residual check
+          // (with the next step's initial data) runs in this window
+          c2_t<T>* tmp = x;
+          x = xo;
+          xo = tmp;
+          st.xsel ^= 1;
+          fused_check();
+          st.matvecs++;
+          st.state = ST_VCHECK;
+        } else {
+          const c2_t<T> al = to_c<T>(st.alpha);
+          const c2_t<T>* dir = prec ? ph : p;
+          elem_own<T>(a, wi, [&](long e) { x[e] = cfma<T>(al, dir[e], x[e]); });
+          converged();
+        }
       } else if constexpr (PREC) {
         chains_own<T, MODE_IN_S>(a, wi, V, base, st.alpha, st.alpha, sh);  // s^ = K^-1 s
         st.precs++;
@@ -608,6 +637,8 @@ void persistent_kernel(SolveArgs a) {
   terms_layout<double>(a.op64, sh.tl2);
   const TermRegs treg = term_regs(a, wi);
   bool ready = false;  // this step's b, x0, r, r^ and partials were formed by the previous step
+  int xsel = 0;        // the iterate of a ready step lives in the second iterate buffer
+  int spec_it = 0;     // the previous step's last iteration (its half step is tested ahead)
   for (int k = 0; k < a.n_chunk; ++k) {
     const int step = a.step0 + k;
     int* cnt = a.counters + (size_t)k * kCounterPerStep;
@@ -633,6 +664,8 @@ void persistent_kernel(SolveArgs a) {
     st.state = inst ? ST_ACTIVE : ST_INACTIVE;
     st.fresh = 1;
     st.first = 1;
+    st.xsel = ready ? xsel : 0;
+    st.spec_it = spec_it;
     st.omega = make_double2(1.0, 0.0);
     st.alpha = make_double2(1.0, 0.0);
     st.rho = make_double2(1.0, 0.0);
@@ -715,8 +748,10 @@ void persistent_kernel(SolveArgs a) {
                                           __HIP_MEMORY_SCOPE_AGENT) == 0;
       int* need_next = chained && k + 1 < a.n_chunk ? a.counters + (size_t)(k + 1) * kCounterPerStep + 1 : nullptr;
       krylov<double, PREC>(a, wk, V, bbuf, base, a.tol, a.max_iter, true, cnt, st, sh, mk, gb, dst, so,
-                           fuse ? bnbuf : nullptr, ready, need_next, skip);
+                           fuse ? bnbuf : nullptr, ready, need_next, skip, a.xalt);
       ready = inst && st.next_ready;
+      xsel = st.xsel;
+      spec_it = st.iters > 0 ? st.iters - 1 : 0;
       if (gb.failed) { fail_steps(a, wi, k); return; }
     } else {
       // ---- FP64 iterative refinement around an FP32 BiCGSTAB (inner residuals, dots in FP64)

@@ -48,6 +48,7 @@ struct tdde_ctx {
   KVec<float> v32np{};
   double2* bvec = nullptr;
   double2* bvec2 = nullptr;
+  double2* xalt = nullptr;  // second iterate buffer (x + alpha p^ formed ahead of the half-step test)
   double2* r64 = nullptr;
   float2* rhs32 = nullptr;
   double2* part = nullptr;
@@ -459,6 +460,7 @@ tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
   if ((s = alloc_kvec<float>(c, c->v32, c->v32np, n)) != TDDE_OK) return s;
   if ((s = dev_alloc(c, &c->bvec, n)) != TDDE_OK) return s;
   if ((s = dev_alloc(c, &c->bvec2, n)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->xalt, n)) != TDDE_OK) return s;
   if ((s = dev_alloc(c, &c->r64, n)) != TDDE_OK) return s;
   if ((s = dev_alloc(c, &c->rhs32, n)) != TDDE_OK) return s;
   if ((s = dev_alloc(c, &c->fvals, (size_t)c->d.batch * c->d.n_fields)) != TDDE_OK) return s;
@@ -816,6 +818,7 @@ static SolveArgs base_args(tdde_ctx* c, const tdde_solve_opts* o) {
   a.v32 = a.use_prec ? c->v32 : c->v32np;
   a.bvec = c->bvec;
   a.bvec2 = c->bvec2;
+  a.xalt = c->xalt;
   a.r64 = c->r64;
   a.rhs32 = c->rhs32;
   a.B = c->d.batch;
