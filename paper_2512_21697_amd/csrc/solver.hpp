@@ -247,7 +247,8 @@ __device__ inline void chains_own(const SolveArgs& a, const WgInfo& wi, const KV
 // r^ = r are already written and their partials (SLOT_RHO, SLOT_RR, SLOT_BB) stored; the
 // unfinished-work-group counter *cnt already counts this work-group. verify: confirm convergence
 // with the true residual (restart on failure). On its final transition an instance writes its
-// iterate to dst (when not null) and its statistics to *so (when not null). The loop ends at the
+// iterate to dst (when not null, and not when the next step in the launch was prepared from it) and
+// its statistics to *so (when not null). The loop ends at the
 // first barrier after which no work-group of the launch is unfinished. need_init (when not null):
 // counter of instances whose next step in the launch must form its own initial data, incremented
 // on the final transition. skip_first: the caller has just passed a grid barrier after which every
@@ -279,11 +280,14 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
 
   // final transition: write back, report, leave the unfinished count (zero_x: the next step starts
   // from a zero guess)
+  // A step whose successor in the launch already has its initial data (next_ready) skips the
+  // write-back: the successor does not read dst, and writes its own result there.
   auto finish = [&](int state, bool zero_x = false) {
     st.state = state;
-    if (dst != nullptr || zero_x)
+    const bool write = dst != nullptr && !(state == ST_DONE && st.next_ready);
+    if (write || zero_x)
       elem_own<T>(a, wi, [&](long e) {
-        if (dst != nullptr) dst[e] = x[e];
+        if (write) dst[e] = x[e];
         if (zero_x) x[e] = cmk<T>(0, 0);
       });
     if (need_init != nullptr && !st.next_ready && wi.g == 0 && threadIdx.x == 0)
