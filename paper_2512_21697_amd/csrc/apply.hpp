@@ -7,9 +7,10 @@
 //
 // Work-group layout: 256 threads = 2 components x 128 radial points; thread (s, ii) owns
 // y[j][s][i0 + ii]. The x tile of channel j (with a halo of hb points) is staged in LDS; the
-// angular combinations w_m = sum_j' A_m[j][j'] x[j'] of all terms sharing one sparsity pattern are
-// staged in LDS together (each neighbouring x value is read once per pattern), so the radial band
-// contraction reads LDS and the angular gather is not repeated per radial tap or per term.
+// angular combinations w_m = sum_j' A_m[j][j'] x[j'] of all terms of one group (terms sharing the
+// union of their sparsity patterns) are staged in LDS together (each neighbouring x value is read
+// once per group), so the radial band contraction reads LDS and the angular gather is not repeated
+// per radial tap or per term.
 #pragma once
 #include "common.hpp"
 
@@ -184,7 +185,7 @@ __device__ inline c2_t<T> ccontract(const CTaps<T>& t, const c2_t<T>* x, c2_t<T>
 // Latency structure: every global load of a phase is issued before its first use, and the
 // branches around loads depend only on the spinor component s, which is uniform over a wave
 // (128 threads per component), so they are scalar branches: H0/S taps are loaded before the
-// staging barrier is passed, coupling bands two terms at a time.
+// staging barrier is passed, coupling bands TR terms at a time.
 // GB: gather batch; TR: coupling terms whose bands are loaded together (registers vs round trips).
 template <typename T, bool TWO = false, int GB = 4, int TR = 2>
 __device__ inline SH<T> apply_tile(const DevOp<T>& op, const c2_t<T>* __restrict__ xinst, int j, int i0,

@@ -11,7 +11,7 @@ constexpr int kTileR = 128;      // radial points per tile (x 2 spinor component
 constexpr int kHB = 6;           // radial half-bandwidth: order-7 B-splines overlap 6 neighbours per side
 constexpr int kMaxHB = kHB;
 constexpr int kMaxTerms = 32;    // largest number of coupling terms
-constexpr int kMaxGroup = 8;     // coupling terms staged together (same angular sparsity pattern)
+constexpr int kMaxGroup = 8;     // coupling terms staged together (one group: union angular pattern)
 constexpr int kMaxFields = 16;   // largest number of time functions per instance
 constexpr int kHalo = kTileR + 2 * kMaxHB;
 
@@ -86,7 +86,7 @@ template <typename T> struct DevOp {
   const T* h_blk;              // [n_kblk][2][2][nb][nr] (null when n_h == 0)
   const c2_t<T>* h_chan;       // [nang][2][2][nb][nr]
   const T* s_blk;              // [n_kblk][2][2][nb][nr] (null when n_s == 0: S = I)
-  // Terms with one angular sparsity pattern form a group and are staged together:
+  // Terms grouped on the host (the union of their angular sparsity patterns) are staged together:
   // group g holds terms g_term[g_first[g] .. g_first[g+1]); its pattern is g_rowptr[g][nang+1]
   // (absolute offsets into g_col); the value of term k of the group at pattern entry p is
   // g_val[g_voff[g] + (p - g_rowptr[g][0]) * K + k], K = group size, with the kappa exponents

@@ -12,12 +12,15 @@
 // Each BiCGSTAB iteration (van der Vorst 1992; right preconditioner K = M of eq. matrixM when
 // enabled) runs in five windows separated by grid barriers:
 //   W0  rho, ||r|| -> convergence / restart decision, beta;  p = r + beta (p - omega v), p^ = K^-1 p
-//   W1  v = A p^, <r^, v>              (VERIFY instances: r = b - A x, ||r||)
-//   W2  alpha;  s = r - alpha v, ||s||   (VERIFY: accept or restart)
+//   W1  v = A p^, <r^, v>
+//   W2  alpha;  s = r - alpha v, ||s||  (and x + alpha p^ into the other iterate buffer when this
+//       half step is expected to end the solve)
 //   W3  ||s|| test (half step);  without preconditioner t = A s, <t, s>, <t, t>; with it s^ = K^-1 s
 //   W3b (preconditioned only) t = A s^, <t, s>, <t, t>
 //   W4  omega;  x += alpha p^ + omega s^,  r = s - omega t,  <r^, r>, ||r||
-// The loop ends when the count of unfinished instances, read right after the W1 barrier, is zero.
+// The true-residual check (VERIFY / VCHECK states) runs in whichever windows follow convergence;
+// when the half step ends the solve with x + alpha p^ already formed, it runs in W3 itself. The loop
+// ends at the first barrier after which the count of unfinished work-groups is zero.
 #pragma once
 #include "apply.hpp"
 #include "precond.hpp"
@@ -29,8 +32,8 @@ namespace tdde {
 enum { ST_INACTIVE = 0, ST_ACTIVE = 1, ST_VERIFY = 2, ST_DONE = 3, ST_FAILED = 4, ST_PENDING = 5, ST_BREAKDOWN = 6,
        ST_VCHECK = 7 };
 // A slot is never read and written in the same barrier window by one instance.
-//   RHO, RR: written W4 (and W1 for VERIFY), read W0 (RR also W2 for VERIFY)
-//   AUX: ||r||^2 of a restart, written W0/W1/W2, read W0 when PENDING
+//   RHO, RR: written W4, read W0; RR also written by a residual check and read in the window after it
+//   AUX: ||r||^2 of a restart, written by a restart or a non-fused residual check, read W0 when PENDING
 //   ORR, OBB: outer refinement residual / rhs norms (mixed precision)
 // SLOT_N*: the next step's initial partials, formed with the residual check of the current step
 enum { SLOT_RHO = 0, SLOT_RR, SLOT_RV, SLOT_SS, SLOT_TS, SLOT_TT, SLOT_BB, SLOT_AUX, SLOT_ORR, SLOT_OBB, SLOT_NRHO,
