@@ -25,6 +25,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WG_PER_CU = 4  # the library's default launch shape (work-groups per CU of the persistent grid)
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -76,23 +77,28 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(wg_per_cu):
     """HBM bytes per launch of the persistent kernel from the committed rocprofv3 counter summary,
-    or None when it is missing or was taken from other kernel sources."""
+    or None when it is missing, was taken from other kernel sources or under another launch
+    shape (work-groups per CU)."""
     path = os.path.join(ROOT, "profiles", "persistent_kernel_hydrogen_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash() or d.get("wg_per_cu") != wg_per_cu:
         return None
     return d
 
 
-def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0):
+def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0, launch=0, info=None):
     """Run warmup + timed steps in persistent chunks.
 
+    launch: work-groups per CU of the persistent grid (1..4, 0 = library default), or "auto" to
+    let the autotuner time one chunk of steps (on a scratch copy of the state, before the warmup)
+    under every shape and keep the fastest; ``info`` (a dict) receives the choice and the timings.
     Returns (ms_per_step, stats array, [(kernel ms, steps) per launch], wall seconds, final state)."""
+    from paper_2512_21697_amd.autotune import tune_launch
     s = P.Solver(w.op, 1)
     s.set_dt(w.dt)
     s.set_pulses(w.pulses)
@@ -100,6 +106,27 @@ def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precisio
                         max_outer=20)
     psi = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
     stream = torch.cuda.current_stream()
+    if launch == "auto":
+        scratch = torch.empty_like(psi)
+        tune_stats = torch.zeros(chunk * 40, dtype=torch.uint8, device="cuda:0")
+        tune_n = np.array([chunk], dtype=np.int32)
+
+        def one_chunk():
+            scratch.copy_(psi)
+            s.run_batched(scratch, w.t0, 0, chunk, tune_n, opts, tune_stats)
+
+        best, times = tune_launch(s, one_chunk, prefer=DEFAULT_WG_PER_CU)
+        del scratch, tune_stats
+        if info is not None:
+            info["wg_per_cu"] = best
+            info["ms_per_chunk"] = {str(k): round(v * 1e3, 3) for k, v in times.items()}
+            info["chunk_steps"] = chunk
+    else:
+        s.set_launch(int(launch))
+        if info is not None:
+            info["wg_per_cu"] = int(launch) or DEFAULT_WG_PER_CU
+    if info is not None:
+        info["n_wg"], info["wg_per_instance"] = s.launch_info()
     total = warmup + steps
     n_steps = np.array([total], dtype=np.int32)
     stats = torch.zeros(total * 40, dtype=torch.uint8, device="cuda:0")
@@ -258,6 +285,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched learned-guess comparison")
     ap.add_argument("--batched-steps", type=int, default=200, help="steps per instance in the batched sections")
+    ap.add_argument("--wg-per-cu", default="auto",
+                    help="persistent work-groups per CU (1..4), or 'auto' to autotune before the warmup")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -275,8 +304,11 @@ def main():
     w = dkb.config2()
     E = w.op.n_unknowns
     _log(f"bench: gpu steps={args.steps} warmup={args.warmup}")
+    launch = args.wg_per_cu if args.wg_per_cu == "auto" else int(args.wg_per_cu)
+    tuning = {}
     ms_step, st, launches, wall, psi64 = run_gpu_steps(P, torch, w, args.steps, args.warmup, precond=1,
-                                                       guess=P.GUESS_PREV)
+                                                       guess=P.GUESS_PREV, launch=launch, info=tuning)
+    _log(f"bench: launch shape {tuning}")
     iters = st["iters"].astype(float)
     mv = st["matvecs"].astype(float)
     ok = bool(np.all(st["status"] == 0))
@@ -286,7 +318,7 @@ def main():
     it_mean = float(iters.mean())
     bytes_step = algorithmic_bytes_per_step(w.op, float(mv.mean()), float(st["precs"].mean()), it_mean)
     achieved = bytes_step * steps_per_launch / (kern_ms * 1e-3) / 1e9
-    tr = measured_traffic()
+    tr = measured_traffic(tuning.get("wg_per_cu"))
     traffic = None
     if tr is not None:
         traffic = (tr["fetch_kib_per_step"] * tr["fetch_scale"] + tr["write_kib_per_step"] * tr["write_scale"]) * 1024.0 \
@@ -307,7 +339,7 @@ def main():
         "config": {"workload": "hydrogen dipole: Nr=2000, Nang=41 (l<=20, mu=1/2), N=164000, dt=2e-4, "
                                "E0=0.05, w=0.057, 8-cycle sin^2, ground-state start, tol 1e-12, "
                                "block-LU preconditioner, previous-state guess",
-                   "batch": 1, "seq_len": None, "parallelism": "single GPU"},
+                   "batch": 1, "seq_len": None, "parallelism": "single GPU", "launch": tuning},
         "iters_per_step": it_mean,
         "matvecs_per_step": float(mv.mean()),
         "precond_solves_per_step": float(st["precs"].mean()),

@@ -179,6 +179,15 @@ tdde_status tdde_run_batched(tdde_ctx* ctx, void* psi_dev, double t0, int32_t st
 /* Release every device buffer of the context. Accepts NULL. */
 tdde_status tdde_destroy(tdde_ctx* ctx);
 
+/* Launch shape of the persistent kernel: at most wg_per_cu work-groups per compute unit (1..4;
+ * 0 restores the default, 4), further capped by each kernel variant's occupancy. The GPU mapping
+ * of the solver's kernels (Sec. 3.3) leaves the number of thread blocks open; this is the knob the
+ * launch autotuner sweeps. Results agree between shapes up to the order of the grid-wide
+ * reductions. Call after tdde_assemble. TDDE_ERR_ARG when wg_per_cu is out of range or the grid
+ * would hold fewer work-groups than instances (nothing is changed then); TDDE_ERR_STATE before
+ * assembly. */
+tdde_status tdde_set_launch(tdde_ctx* ctx, int32_t wg_per_cu);
+
 /* Persistent-grid size actually used (work-groups) and the per-instance work-group count. */
 tdde_status tdde_launch_info(tdde_ctx* ctx, int32_t* n_wg, int32_t* wg_per_instance);
 

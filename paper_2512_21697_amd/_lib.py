@@ -59,7 +59,7 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"),
 
 EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field", "tdde_apply",
            "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_step", "tdde_run_batched", "tdde_destroy",
-           "tdde_launch_info", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
+           "tdde_launch_info", "tdde_set_launch", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
            "tdde_debug_read_marks", "tdde_mlp_create", "tdde_mlp_destroy",
            "tdde_mlp_param_count", "tdde_mlp_set_params", "tdde_mlp_get_params", "tdde_mlp_get_grads",
            "tdde_mlp_forward", "tdde_mlp_backward", "tdde_mlp_adam", "tdde_mlp_set_pulses", "tdde_mlp_guess",
@@ -91,6 +91,7 @@ def load():
         "tdde_run_batched": [P, P, C.c_double, C.c_int32, C.c_int32, P, P, C.POINTER(SolveOpts), P],
         "tdde_destroy": [P],
         "tdde_launch_info": [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+        "tdde_set_launch": [P, C.c_int32],
         "tdde_debug_phase_marks": [P, C.c_int32],
         "tdde_debug_read_marks": [P, P, C.c_int32],
     }
@@ -317,6 +318,10 @@ class Solver:
         a = a[a != 0]
         t = (a >> np.uint64(8)).astype(np.float64) / 100.0  # 100 MHz wall clock -> microseconds
         return list(zip((t - t[0]).tolist(), (a & np.uint64(0xFF)).astype(int).tolist())) if len(a) else []
+
+    def set_launch(self, wg_per_cu: int):
+        """At most wg_per_cu persistent work-groups per CU (1..4; 0 = default)."""
+        self._check(self.lib.tdde_set_launch(self.h, int(wg_per_cu)))
 
     def launch_info(self):
         a, b = C.c_int32(), C.c_int32()

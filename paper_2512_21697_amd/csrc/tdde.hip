@@ -19,6 +19,9 @@
 using namespace tdde;
 using cd = std::complex<double>;
 
+// Most persistent work-groups placed on one CU (the default launch shape).
+constexpr int kMaxWgPerCu = 4;
+
 struct tdde_ctx {
   tdde_dims d{};
   hipStream_t stream = nullptr;
@@ -62,6 +65,8 @@ struct tdde_ctx {
   int* n_steps_dev = nullptr;
   int n_wg = 0, G = 0;          // grid of the variant in use (set per launch)
   int var_wg[4] = {0, 0, 0, 0};  // co-resident work-groups of each persistent-kernel variant
+  int var_occ[4] = {0, 0, 0, 0}; // occupancy limit (work-groups per CU) of each variant
+  int ncu = 0;
   unsigned long long* marks = nullptr;
   int n_marks = 0;
 };
@@ -474,10 +479,12 @@ tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
     int per_cu = 0;
     HIP_TRY(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_variant(v), kThreads, 0));
     if (per_cu <= 0) return fail(c, TDDE_ERR_HIP, "persistent kernel cannot be resident");
-    c->var_wg[v] = ncu * std::min(per_cu, 4);
+    c->var_occ[v] = per_cu;
+    c->var_wg[v] = ncu * std::min(per_cu, kMaxWgPerCu);
     if (c->d.batch > c->var_wg[v]) return fail(c, TDDE_ERR_ARG, "batch larger than the co-resident work-group count");
     max_wg = std::max(max_wg, c->var_wg[v]);
   }
+  c->ncu = ncu;
   c->n_wg = c->var_wg[0];
   c->G = c->n_wg / c->d.batch;
   if ((s = dev_alloc(c, &c->part, (size_t)max_wg * kSlots)) != TDDE_OK) return s;
@@ -508,6 +515,23 @@ tdde_status tdde_debug_read_marks(tdde_ctx* c, uint64_t* host, int32_t cap) {
   if (!c->marks) return fail(c, TDDE_ERR_STATE, "enable phase marks first");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipMemcpy(host, c->marks, (size_t)std::min(cap, c->n_marks) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  return TDDE_OK;
+}
+
+tdde_status tdde_set_launch(tdde_ctx* c, int32_t wg_per_cu) {
+  if (!c) return fail(c, TDDE_ERR_ARG, "null context");
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  if (wg_per_cu < 0 || wg_per_cu > kMaxWgPerCu) return fail(c, TDDE_ERR_ARG, "wg_per_cu must be 0..4");
+  const int k = wg_per_cu == 0 ? kMaxWgPerCu : wg_per_cu;
+  int wg[4];
+  for (int v = 0; v < 4; ++v) {
+    wg[v] = c->ncu * std::min(c->var_occ[v], k);
+    if (c->d.batch > wg[v]) return fail(c, TDDE_ERR_ARG, "batch larger than the requested work-group count");
+  }
+  // the partial-sum buffer was sized for the largest grid at assembly; grids only shrink here
+  for (int v = 0; v < 4; ++v) c->var_wg[v] = wg[v];
+  c->n_wg = c->var_wg[0];
+  c->G = c->n_wg / c->d.batch;
   return TDDE_OK;
 }
 

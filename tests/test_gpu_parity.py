@@ -295,3 +295,90 @@ def test_multistep_launch_matches_oracle(gpu, case):
         assert np.all(st["status"] == 0), st
         assert np.all(st["true_rel_res"] <= tol), st["true_rel_res"]
         assert err < 1e-10 * n, err
+
+
+@pytest.mark.parametrize("wg_per_cu", [1, 2, 3, 4])
+def test_launch_shapes_match_oracle(gpu, wg_per_cu):
+    """Every persistent launch shape gives the oracle's states: the preconditioned hydrogen case
+    (one instance spread over the whole grid) and three uneven instances in one launch."""
+    P = _lib()
+    w = dkb.config2(nr=300, r_max=60.0, lmax=3, driven=True, E0=0.5)
+    n = 4
+    s = P.Solver(w.op, 1)
+    s.set_dt(w.dt)
+    s.set_pulses(w.pulses)
+    n_wg_default, _ = s.launch_info()
+    s.set_launch(wg_per_cu)
+    n_wg, per_inst = s.launch_info()
+    assert 1 <= per_inst <= n_wg <= n_wg_default
+    psi = _dev(w.psi0).reshape(-1).clone()
+    stats = torch.zeros(n * 40, dtype=torch.uint8, device=DEV)
+    s.run_batched(psi, w.t0, 0, n, np.array([n], dtype=np.int32),
+                  P.solve_opts(tol=1e-12, max_iter=100, guess=P.GUESS_PREV, precond=1), stats)
+    torch.cuda.synchronize()
+    st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+    assert np.all(st["status"] == 0), st
+    got = psi.cpu().numpy().reshape(w.op.nang, 2, w.op.nr)
+    asm = Assembled(w.op)
+    ref = w.psi0[0]
+    for k in range(n):
+        ref, _ = cn_step(asm, w.pulses[0], w.t0 + k * w.dt, w.dt, ref, solver="splu")
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 1e-10 * n, err
+    s.close()
+
+    wb = synthetic.config5(batch=3, nr=200, nang=6, seeds=[10001, 10002, 10003])
+    n_steps = np.array([5, 3, 4], dtype=np.int32)
+    sb = P.Solver(wb.op, 3)
+    sb.set_dt(wb.dt)
+    sb.set_pulses(wb.pulses)
+    sb.set_launch(wg_per_cu)
+    psi = _dev(wb.psi0).reshape(-1).clone()
+    stats = torch.zeros(5 * 3 * 40, dtype=torch.uint8, device=DEV)
+    sb.run_batched(psi, wb.t0, 0, 5, n_steps, P.solve_opts(tol=1e-12, guess=P.GUESS_ZERO), stats)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy().reshape(3, wb.op.nang, 2, wb.op.nr)
+    st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE).reshape(5, 3)
+    asm = Assembled(wb.op)
+    for b in range(3):
+        ref = wb.psi0[b]
+        for k in range(int(n_steps[b])):
+            ref, _ = cn_step(asm, wb.pulses[b], wb.t0 + k * wb.dt, wb.dt, ref, solver="splu")
+            assert st[k, b]["status"] == 0
+        err = np.linalg.norm(got[b] - ref) / np.linalg.norm(ref)
+        assert err < 1e-10 * n_steps[b], (b, err)
+    sb.close()
+
+
+def test_launch_shape_errors_and_autotune(gpu):
+    """Out-of-range shapes are rejected and leave the grid unchanged; the autotuner leaves the
+    solver on the shape it reports as fastest."""
+    from paper_2512_21697_amd.autotune import tune_launch
+    P = _lib()
+    w = synthetic.config1(driven=True)
+    s = P.Solver(w.op, 1)
+    s.set_dt(w.dt)
+    s.set_pulses(w.pulses)
+    before = s.launch_info()
+    for bad in (-1, 5):
+        with pytest.raises(P.TddeError):
+            s.set_launch(bad)
+    assert s.launch_info() == before
+    s.set_launch(1)
+    s.set_launch(0)
+    assert s.launch_info() == before
+    psi0 = _dev(w.psi0).reshape(-1)
+    scratch = torch.empty_like(psi0)
+    stats = torch.zeros(8 * 40, dtype=torch.uint8, device=DEV)
+    opts = P.solve_opts(tol=1e-12, guess=P.GUESS_PREV)
+
+    def run():
+        scratch.copy_(psi0)
+        s.run_batched(scratch, w.t0, 0, 8, np.array([8], dtype=np.int32), opts, stats)
+
+    best, times = tune_launch(s, run, reps=2)
+    assert set(times) == {1, 2, 3, 4} and best == min(times, key=times.get)
+    torch.cuda.synchronize()
+    st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+    assert np.all(st["status"] == 0)
+    s.close()
