@@ -185,6 +185,31 @@ def mixed_section(P, torch, w, steps, warmup, psi64):
             "state_rel_diff_vs_fp64_after_steps": diff, "s_norm_drift": abs(n1 - n0)}
 
 
+def tune_batched(P, torch, w5, steps=8):
+    """Autotune the persistent launch shape of the batched sweep: one launch of ``steps`` zero-guess
+    steps of every instance, on a scratch copy of the states, per shape."""
+    from paper_2512_21697_amd.autotune import tune_launch
+    s = P.Solver(w5.op, w5.batch)
+    s.set_dt(w5.dt)
+    s.set_pulses(w5.pulses)
+    psi = torch.from_numpy(np.ascontiguousarray(w5.psi0.reshape(-1))).to("cuda:0")
+    scratch = torch.empty_like(psi)
+    stats = torch.zeros(steps * w5.batch * P.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+    ns = np.full(w5.batch, steps, dtype=np.int32)
+    opts = P.solve_opts(tol=1e-12, max_iter=300, guess=P.GUESS_ZERO)
+
+    def one_launch():
+        scratch.copy_(psi)
+        s.run_batched(scratch, w5.t0, 0, steps, ns, opts, stats)
+
+    best, times = tune_launch(s, one_launch, prefer=DEFAULT_WG_PER_CU)
+    n_wg, per_inst = s.launch_info()
+    s.close()
+    del psi, scratch, stats
+    return {"wg_per_cu": best, "ms_per_launch": {str(k): round(v * 1e3, 3) for k, v in times.items()},
+            "launch_steps": steps, "n_wg": n_wg, "wg_per_instance": per_inst}
+
+
 def batched_learned_section(P, torch, train_steps, eval_steps, n_train=200, train_batch=50, log=None):
     """Batched sweep (64 instances of the block-banded recipe at Nr = 2000, Nang = 41) with zero,
     previous-state, fitted-skip and full-network guesses; the network is trained on solver
@@ -212,12 +237,16 @@ def batched_learned_section(P, torch, train_steps, eval_steps, n_train=200, trai
     losses = learned.train(torch, net, raw, n_iter=800, batch_rows=16384, lr=1e-3)
     t_train = time.perf_counter() - t0
     ns = np.minimum(w5.n_steps, eval_steps)
+    launch = tune_batched(P, torch, w5)
+    if log:
+        log(f"bench: batched launch shape {launch}")
     out = {"instances": int(w5.batch), "train_rows": int(raw.shape[0]), "collect_s": t_collect, "train_s": t_train,
            "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-50:].mean()),
-           "skip_sigma": float(net.get_skip()[1])}
+           "skip_sigma": float(net.get_skip()[1]), "launch": launch}
     ref = None
     for mode in ("zero", "prev", "skip", "mlp"):
-        fin, st, el = learned.propagate(torch, op, w5.pulses, ns, w5.psi0, w5.dt, mode, net=net)
+        fin, st, el = learned.propagate(torch, op, w5.pulses, ns, w5.psi0, w5.dt, mode, net=net,
+                                        wg_per_cu=launch["wg_per_cu"])
         act = learned.active_mask(ns, st.shape[0])
         if ref is None:
             ref = fin

@@ -112,9 +112,10 @@ def train(torch, net: Net, raw, n_iter=1500, batch_rows=8192, lr=1e-3, seed=0, l
     return np.array(losses)
 
 
-def propagate(torch, op, pulses, n_steps, psi0, dt, mode, net: Net | None = None, t0=0.0, chunk=32):
+def propagate(torch, op, pulses, n_steps, psi0, dt, mode, net: Net | None = None, t0=0.0, chunk=32, wg_per_cu=0):
     """Run every instance to its own length with guess mode "zero", "prev", "skip" (the network's
-    fitted linear part alone) or "mlp" (the whole network).
+    fitted linear part alone) or "mlp" (the whole network). wg_per_cu: launch shape of the
+    persistent grid (0 = library default).
 
     Returns (final states [B*E] tensor, per-step stats array [steps][B], elapsed seconds)."""
     B = len(pulses)
@@ -122,6 +123,7 @@ def propagate(torch, op, pulses, n_steps, psi0, dt, mode, net: Net | None = None
     s = Solver(op, B)
     s.set_dt(dt)
     s.set_pulses(pulses)
+    s.set_launch(wg_per_cu)
     dev = "cuda:0"
     ns = np.asarray(n_steps, dtype=np.int32)
     total = int(ns.max())
