@@ -7,7 +7,9 @@ LU factors) the search directions are p_hat = K^-1 p and s_hat = K^-1 s, A acts 
 those, and x is updated with them; r stays the residual of the original system.
 Stopping rule: ||r|| <= tol ||b|| on the recursive residual (also tested on s after
 the half step), then the true residual b - A x is checked once; if it fails, the
-iteration restarts from the current x. A vanishing rho or omega also restarts.
+iteration restarts from the current x. A vanishing rho, <r^, v> or omega restarts with
+r^ = r (van der Vorst leaves the shadow residual r^ free as long as <r^, r0> != 0; a
+restart is the standard remedy when one of the three scalars becomes zero).
 """
 from __future__ import annotations
 
@@ -30,9 +32,13 @@ def _dot(a, b):
     return np.vdot(a, b)
 
 
-def bicgstab(A, b: np.ndarray, x0: np.ndarray | None, tol: float = 1e-12, max_iter: int = 1000, precond=None):
+def bicgstab(A, b: np.ndarray, x0: np.ndarray | None, tol: float = 1e-12, max_iter: int = 1000, precond=None,
+             rhat0: np.ndarray | None = None, max_restarts: int = 20):
     """Solve A x = b. A is anything with ``@`` (scipy sparse or dense); precond is None or a
-    callable z -> K^-1 z. Returns (x, SolveStats)."""
+    callable z -> K^-1 z. rhat0: shadow residual of the first cycle (default r0; later cycles
+    after a restart always take r^ = r). More than max_restarts restarts end the solve
+    unconverged (a Krylov space that breaks down again after every restart makes no progress).
+    Returns (x, SolveStats)."""
     apply_k = (lambda z: z) if precond is None else precond
     st = SolveStats()
     x = np.zeros_like(b) if x0 is None else x0.astype(np.complex128).copy()
@@ -47,8 +53,10 @@ def bicgstab(A, b: np.ndarray, x0: np.ndarray | None, tol: float = 1e-12, max_it
         st.converged = True
         st.rel_res = st.true_rel_res = np.linalg.norm(r) / bnorm
         return x, st
+    first_cycle = True
     while True:
-        rhat = r.copy()
+        rhat = r.copy() if (rhat0 is None or not first_cycle) else np.asarray(rhat0, dtype=np.complex128).copy()
+        first_cycle = False
         rho_old = alpha = omega = 1.0 + 0.0j
         v = np.zeros_like(b)
         p = np.zeros_like(b)
@@ -63,7 +71,11 @@ def bicgstab(A, b: np.ndarray, x0: np.ndarray | None, tol: float = 1e-12, max_it
             ph = apply_k(p)
             v = A @ ph
             st.matvecs += 1
-            alpha = rho / _dot(rhat, v)
+            rv = _dot(rhat, v)
+            if rv == 0:
+                st.restarts += 1
+                break
+            alpha = rho / rv
             s = r - alpha * v
             st.iters += 1
             if np.linalg.norm(s) <= target:
@@ -100,6 +112,8 @@ def bicgstab(A, b: np.ndarray, x0: np.ndarray | None, tol: float = 1e-12, max_it
             break
         if done:
             st.restarts += 1
+        if st.restarts > max_restarts:
+            break
     if not st.converged:
         r = b - A @ x
         st.true_rel_res = np.linalg.norm(r) / bnorm
