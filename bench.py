@@ -1,20 +1,30 @@
 """Benchmark of the Crank-Nicolson / BiCGSTAB time step on one MI355X.
 
-Default workload: the hydrogen dipole case (DKB B-splines, Nr = 2000 radial pairs on [0, 200],
-41 kappa channels at mu = 1/2, N = 164000 complex128 unknowns, dt = 2e-4, ground state start,
-sin^2 pulse with 8 cycles at omega = 0.057, E0 = 0.05), preconditioned FP64 BiCGSTAB to a relative
-residual of 1e-12. One "step" is one full time step of the hot path: field evaluation at the
-midpoint, right-hand side, initial guess, BiCGSTAB with the block LU preconditioner, true-residual
-check. Steps run in persistent launches of up to 64 steps; the timed region starts with the
-inputs resident in HBM.
+Headline workload: the beyond-dipole single-GPU share (Nr = 4000 order-7 radial functions per
+component, 770 angular channels with l <= 40 and |mu| <= 9/2, six coupling terms with |dl| <= 2,
+mu' = mu +- 1; N = 6.16e6 complex128 unknowns), sin^2 pulses at omega and omega +- 2 pi / T
+(E0 = 0.05, T = 20, dt = 1e-3), started mid-pulse at t = T/4 so the coupling is switched on,
+FP64 BiCGSTAB to a relative residual of 1e-12, right-preconditioned by the block LU of
+M = S + i dt/2 H0 (the paper's setting), previous-state guess. One "step" is one full time step of
+the hot path: field evaluation at the midpoint, right-hand side, initial guess, BiCGSTAB with the
+preconditioner, true-residual check. Steps run in persistent launches of up to 64 steps; the
+timed region starts with every input resident in HBM.
+
+Sub-lines (same JSON line): the same workload without the preconditioner, its standalone operator
+apply, the hydrogen dipole case (ground state at t = 0, and mid-pulse with E0 = 0.5), the small
+block-banded case (from t = 0 and from t = T/4), mixed precision on the hydrogen operator, the
+64-instance batched sweep with zero / previous / fitted-skip / learned guesses, and the oracle on
+the host cores.
 
 Prints one JSON line (rank 0).
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
+import platform
 import sys
 import time
 
@@ -25,17 +35,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-DEFAULT_WG_PER_CU = 4  # the library's default launch shape (work-groups per CU of the persistent grid)
 FP64_PEAK_TFLOPS = 78.6
+DEFAULT_WG_PER_CU = 4  # the library's default launch shape (work-groups per CU of the persistent grid)
+SECTIONS = ("c3plain", "apply", "c2", "c2d", "c1", "mixed", "batched", "cpu")
 
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# ------------------------------------------------------------------------------ algorithmic counts
+
 def operator_bytes(op):
     """Operator data a matrix-free apply reads at least once: the kappa-polynomial H0 / S bands, the
-    coupling bands and angular values, the per-channel complex bands."""
+    coupling bands and angular values (8-byte value + 4-byte column), the per-channel complex bands."""
     n = op.h_poly.size * 8 + op.s_poly.size * 8 + sum(t.r_band.size * 8 + t.a_val.size * 12 for t in op.terms)
     if op.h_chan is not None:
         n += op.h_chan.size * 16
@@ -47,11 +60,37 @@ def apply_bytes(op):
     return 2 * op.n_unknowns * 16 + operator_bytes(op)
 
 
+def apply_flops(op):
+    """Real floating-point operations of one apply y = a_S S x + a_H H x (FMA = 2), per element:
+    every H0 / S tap block (real taps: 4 flop, complex: 8), for every coupling term the angular
+    combination over its row (real value x complex: 4 flop per entry) and its radial taps
+    (4 flop per tap and nonzero (s, s') block), the complex term prefactor (8) and the final
+    combination (16)."""
+    nb = 2 * op.hb + 1
+    E = op.n_unknowns
+    blk_h = sum(int(np.any(op.h_poly[:, s, s2] != 0)) for s in range(2) for s2 in range(2)) / 2.0
+    blk_s = sum(int(np.any(op.s_poly[:, s, s2] != 0)) for s in range(2) for s2 in range(2)) / 2.0
+    per = nb * 4 * (blk_h + blk_s)
+    if op.h_chan is not None:
+        per += nb * 8 * sum(int(np.any(op.h_chan[:, s, s2] != 0)) for s in range(2) for s2 in range(2)) / 2.0
+    for t in op.terms:
+        nnz_row = len(t.a_col) / op.nang
+        blk = sum(int(np.any(t.r_band[s, s2] != 0)) for s in range(2) for s2 in range(2)) / 2.0
+        per += nnz_row * 4 * max(blk, 1.0) + nb * 4 * blk + 8
+    return (per + 16) * E
+
+
+def factor_blocks(op):
+    """Distinct diagonal blocks of M = S + i dt/2 H0: one per channel with its own complex band,
+    else one per distinct kappa."""
+    return op.nang if op.h_chan is not None else len(np.unique(op.kappa))
+
+
 def prec_bytes(op):
-    """One block preconditioner solve: every channel's banded L and U factors (2 w + 1 complex
-    values per row) read once, input read and output written."""
+    """One block-preconditioner solve: the banded L and U factors (2 w + 1 complex values per row,
+    w = 2 hb + 1) of every distinct block read once, input read, output written."""
     w = 2 * op.hb + 1
-    return op.nang * 2 * op.nr * (2 * w + 1) * 16 + 2 * op.n_unknowns * 16
+    return factor_blocks(op) * 2 * op.nr * (2 * w + 1) * 16 + 2 * op.n_unknowns * 16
 
 
 def algorithmic_bytes_per_step(op, matvecs, precs, iters):
@@ -77,22 +116,24 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(wg_per_cu):
-    """HBM bytes per launch of the persistent kernel from the committed rocprofv3 counter summary,
-    or None when it is missing, was taken from other kernel sources or under another launch
-    shape (work-groups per CU)."""
-    path = os.path.join(ROOT, "profiles", "persistent_kernel_hydrogen_counters.json")
+def measured_traffic(name, launch_key):
+    """HBM bytes per step of the persistent kernel from the committed rocprofv3 counter summary
+    ``profiles/persistent_kernel_<name>_counters.json``, or None when it is missing, was taken from
+    other kernel sources or under another launch shape."""
+    path = os.path.join(ROOT, "profiles", f"persistent_kernel_{name}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != source_hash() or d.get("wg_per_cu") != wg_per_cu:
+    if d.get("source_hash") != source_hash() or d.get("launch") != launch_key:
         return None
     return d
 
 
+# ------------------------------------------------------------------------------ GPU runs
+
 def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0, launch=0, info=None):
-    """Run warmup + timed steps in persistent chunks.
+    """Run warmup + timed steps of one instance in persistent chunks.
 
     launch: work-groups per CU of the persistent grid (1..4, 0 = library default), or "auto" to
     let the autotuner time one chunk of steps (on a scratch copy of the state, before the warmup)
@@ -100,86 +141,117 @@ def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precisio
     Returns (ms_per_step, stats array, [(kernel ms, steps) per launch], wall seconds, final state)."""
     from paper_2512_21697_amd.autotune import tune_launch
     s = P.Solver(w.op, 1)
-    s.set_dt(w.dt)
-    s.set_pulses(w.pulses)
-    opts = P.solve_opts(tol=1e-12, max_iter=200, guess=guess, precond=precond, precision=precision, inner_tol=1e-5,
-                        max_outer=20)
-    psi = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
-    stream = torch.cuda.current_stream()
-    if launch == "auto":
-        scratch = torch.empty_like(psi)
-        tune_stats = torch.zeros(chunk * 40, dtype=torch.uint8, device="cuda:0")
-        tune_n = np.array([chunk], dtype=np.int32)
+    try:
+        s.set_dt(w.dt)
+        s.set_pulses(w.pulses)
+        opts = P.solve_opts(tol=1e-12, max_iter=300, guess=guess, precond=precond, precision=precision,
+                            inner_tol=1e-5, max_outer=20)
+        psi = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
+        stream = torch.cuda.current_stream()
+        if launch == "auto":
+            scratch = torch.empty_like(psi)
+            tune_stats = torch.zeros(chunk * 40, dtype=torch.uint8, device="cuda:0")
+            tune_n = np.array([chunk], dtype=np.int32)
 
-        def one_chunk():
-            scratch.copy_(psi)
-            s.run_batched(scratch, w.t0, 0, chunk, tune_n, opts, tune_stats)
+            def one_chunk():
+                scratch.copy_(psi)
+                s.run_batched(scratch, w.t0, 0, chunk, tune_n, opts, tune_stats)
 
-        best, times = tune_launch(s, one_chunk, prefer=DEFAULT_WG_PER_CU)
-        del scratch, tune_stats
+            best, times = tune_launch(s, one_chunk, prefer=DEFAULT_WG_PER_CU)
+            del scratch, tune_stats
+            if info is not None:
+                info["wg_per_cu"] = best
+                info["ms_per_chunk"] = {str(k): round(v * 1e3, 3) for k, v in times.items()}
+                info["chunk_steps"] = chunk
+        else:
+            s.set_launch(int(launch))
+            if info is not None:
+                info["wg_per_cu"] = int(launch) or DEFAULT_WG_PER_CU
         if info is not None:
-            info["wg_per_cu"] = best
-            info["ms_per_chunk"] = {str(k): round(v * 1e3, 3) for k, v in times.items()}
-            info["chunk_steps"] = chunk
-    else:
-        s.set_launch(int(launch))
-        if info is not None:
-            info["wg_per_cu"] = int(launch) or DEFAULT_WG_PER_CU
-    if info is not None:
-        info["n_wg"], info["wg_per_instance"] = s.launch_info()
-    total = warmup + steps
-    n_steps = np.array([total], dtype=np.int32)
-    stats = torch.zeros(total * 40, dtype=torch.uint8, device="cuda:0")
-    # warmup
-    k = 0
-    while k < warmup:
-        n = min(chunk, warmup - k)
-        s.run_batched(psi, w.t0, k, n, n_steps, opts, stats[k * 40:(k + n) * 40])
-        k += n
-    torch.cuda.synchronize()
-    evs = []
-    t0 = time.perf_counter()
-    start = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    while k < total:
-        n = min(chunk, total - k)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        s.run_batched(psi, w.t0, k, n, n_steps, opts, stats[k * 40:(k + n) * 40])
-        e1.record(stream)
-        evs.append((e0, e1, n))
-        k += n
-    end = torch.cuda.Event(enable_timing=True)
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end)
-    launches = [(a.elapsed_time(b), n) for a, b, n in evs]
-    st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
-    s.close()
+            info["n_wg"], info["wg_per_instance"] = s.launch_info()
+        total = warmup + steps
+        n_steps = np.array([total], dtype=np.int32)
+        stats = torch.zeros(total * 40, dtype=torch.uint8, device="cuda:0")
+        k = 0
+        while k < warmup:
+            n = min(chunk, warmup - k)
+            s.run_batched(psi, w.t0, k, n, n_steps, opts, stats[k * 40:(k + n) * 40])
+            k += n
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        while k < total:
+            n = min(chunk, total - k)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.run_batched(psi, w.t0, k, n, n_steps, opts, stats[k * 40:(k + n) * 40])
+            e1.record(stream)
+            evs.append((e0, e1, n))
+            k += n
+        end = torch.cuda.Event(enable_timing=True)
+        end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = start.elapsed_time(end)
+        launches = [(a.elapsed_time(b), n) for a, b, n in evs]
+        st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+    finally:
+        s.close()
     return ms / steps, st[warmup:], launches, wall, psi
+
+
+def step_summary(w, ms, st, launches):
+    iters = st["iters"].astype(float)
+    mv = st["matvecs"].astype(float)
+    pc = st["precs"].astype(float)
+    kern_ms = sum(t for t, _ in launches) / max(1, len(launches))
+    per_launch = sum(n for _, n in launches) / max(1, len(launches))
+    bytes_step = algorithmic_bytes_per_step(w.op, float(mv.mean()), float(pc.mean()), float(iters.mean()))
+    return {"steps_per_s": 1000.0 / ms, "ms_per_step": ms, "iters_per_step": float(iters.mean()),
+            "matvecs_per_step": float(mv.mean()), "precond_solves_per_step": float(pc.mean()),
+            "all_converged": bool(np.all(st["status"] == 0)), "max_true_rel_res": float(st["true_rel_res"].max()),
+            "kernel_ms_per_launch": kern_ms, "steps_per_launch": per_launch, "alg_bytes_per_step": bytes_step,
+            "alg_GBps": bytes_step * per_launch / (kern_ms * 1e-3) / 1e9}
+
+
+def step_section(P, torch, w, steps, warmup, precond, guess=None, launch=0, label=""):
+    guess = P.GUESS_PREV if guess is None else guess
+    info = {}
+    ms, st, launches, wall, psi = run_gpu_steps(P, torch, w, steps, warmup, precond, guess, launch=launch, info=info)
+    out = step_summary(w, ms, st, launches)
+    out.update({"workload": label, "steps": steps, "precond": bool(precond),
+                "guess": {0: "zero", 1: "previous", 2: "given"}[guess], "launch": info})
+    del psi
+    return out
 
 
 def s_norm(P, torch, op, psi):
     """psi^H S psi with the library's apply (S x: a_s = 1, a_h = 0)."""
     s = P.Solver(op, 1)
-    s.set_field(np.zeros((1, op.n_fields)))
-    y = torch.empty_like(psi)
-    s.apply(psi, y, 1.0, 0.0)
-    torch.cuda.synchronize()
-    s.close()
-    return float(torch.vdot(psi, y).real.item())
+    try:
+        s.set_field(np.zeros((1, op.n_fields)))
+        y = torch.empty_like(psi)
+        s.apply(psi, y, 1.0, 0.0)
+        torch.cuda.synchronize()
+        v = float(torch.vdot(psi, y).real.item())
+    finally:
+        s.close()
+    return v
 
 
-def mixed_section(P, torch, w, steps, warmup, psi64):
+def mixed_section(P, torch, w, steps, warmup):
     """FP32-inner / FP64-refinement solve on the hydrogen operator vs the FP64 path (same steps)."""
+    ms64, st64, _, _, psi64 = run_gpu_steps(P, torch, w, steps, warmup, precond=1, guess=P.GUESS_PREV)
     ms, st, launches, wall, psi = run_gpu_steps(P, torch, w, steps, warmup, precond=1, guess=P.GUESS_PREV,
                                                 precision=P.PREC_MIXED)
     diff = float(torch.linalg.vector_norm(psi - psi64).item() / torch.linalg.vector_norm(psi64).item())
     n0 = s_norm(P, torch, w.op, torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0"))
     n1 = s_norm(P, torch, w.op, psi)
-    return {"ms_per_step": ms, "steps_per_s": 1000.0 / ms, "outer_iters_per_step": float(st["outer_iters"].mean()),
+    return {"steps": steps, "ms_per_step": ms, "steps_per_s": 1000.0 / ms, "fp64_steps_per_s": 1000.0 / ms64,
+            "speedup_vs_fp64": ms64 / ms, "outer_iters_per_step": float(st["outer_iters"].mean()),
             "inner_iters_per_step": float(st["iters"].mean()), "all_converged": bool(np.all(st["status"] == 0)),
             "max_true_rel_res": float(st["true_rel_res"].max()),
             "state_rel_diff_vs_fp64_after_steps": diff, "s_norm_drift": abs(n1 - n0)}
@@ -190,22 +262,24 @@ def tune_batched(P, torch, w5, steps=8):
     steps of every instance, on a scratch copy of the states, per shape."""
     from paper_2512_21697_amd.autotune import tune_launch
     s = P.Solver(w5.op, w5.batch)
-    s.set_dt(w5.dt)
-    s.set_pulses(w5.pulses)
-    psi = torch.from_numpy(np.ascontiguousarray(w5.psi0.reshape(-1))).to("cuda:0")
-    scratch = torch.empty_like(psi)
-    stats = torch.zeros(steps * w5.batch * P.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
-    ns = np.full(w5.batch, steps, dtype=np.int32)
-    opts = P.solve_opts(tol=1e-12, max_iter=300, guess=P.GUESS_ZERO)
+    try:
+        s.set_dt(w5.dt)
+        s.set_pulses(w5.pulses)
+        psi = torch.from_numpy(np.ascontiguousarray(w5.psi0.reshape(-1))).to("cuda:0")
+        scratch = torch.empty_like(psi)
+        stats = torch.zeros(steps * w5.batch * P.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+        ns = np.full(w5.batch, steps, dtype=np.int32)
+        opts = P.solve_opts(tol=1e-12, max_iter=300, guess=P.GUESS_ZERO)
 
-    def one_launch():
-        scratch.copy_(psi)
-        s.run_batched(scratch, w5.t0, 0, steps, ns, opts, stats)
+        def one_launch():
+            scratch.copy_(psi)
+            s.run_batched(scratch, w5.t0, 0, steps, ns, opts, stats)
 
-    best, times = tune_launch(s, one_launch, prefer=DEFAULT_WG_PER_CU)
-    n_wg, per_inst = s.launch_info()
-    s.close()
-    del psi, scratch, stats
+        best, times = tune_launch(s, one_launch, prefer=DEFAULT_WG_PER_CU)
+        n_wg, per_inst = s.launch_info()
+        del psi, scratch, stats
+    finally:
+        s.close()
     return {"wg_per_cu": best, "ms_per_launch": {str(k): round(v * 1e3, 3) for k, v in times.items()},
             "launch_steps": steps, "n_wg": n_wg, "wg_per_instance": per_inst}
 
@@ -230,61 +304,144 @@ def batched_learned_section(P, torch, train_steps, eval_steps, n_train=200, trai
         if log:
             log(f"bench: collected trajectories {k + len(seeds)}/{n_train}")
     raw = torch.cat(rows, 0)
+    del rows
     t_collect = time.perf_counter() - t0
     net = P.Net(16384, 1e-6)
-    net.set_params(learned.init_params(0, net.n_params))
-    t0 = time.perf_counter()
-    losses = learned.train(torch, net, raw, n_iter=800, batch_rows=16384, lr=1e-3)
-    t_train = time.perf_counter() - t0
-    ns = np.minimum(w5.n_steps, eval_steps)
-    launch = tune_batched(P, torch, w5)
-    if log:
-        log(f"bench: batched launch shape {launch}")
-    out = {"instances": int(w5.batch), "train_rows": int(raw.shape[0]), "collect_s": t_collect, "train_s": t_train,
-           "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-50:].mean()),
-           "skip_sigma": float(net.get_skip()[1]), "launch": launch}
-    ref = None
-    for mode in ("zero", "prev", "skip", "mlp"):
-        fin, st, el = learned.propagate(torch, op, w5.pulses, ns, w5.psi0, w5.dt, mode, net=net,
-                                        wg_per_cu=launch["wg_per_cu"])
-        act = learned.active_mask(ns, st.shape[0])
-        if ref is None:
-            ref = fin
-        d = float(torch.linalg.vector_norm(fin - ref).item() / torch.linalg.vector_norm(ref).item())
-        out[mode] = {"iters_per_step": float(st["iters"][act].mean()), "instance_steps_per_s": float(act.sum() / el),
-                     "batched_steps_per_s": float(st.shape[0] / el), "all_converged": bool(np.all(st["status"][act] == 0)),
-                     "rel_diff_vs_zero_guess": d}
+    try:
+        net.set_params(learned.init_params(0, net.n_params))
+        t0 = time.perf_counter()
+        losses = learned.train(torch, net, raw, n_iter=800, batch_rows=16384, lr=1e-3)
+        t_train = time.perf_counter() - t0
+        ns = np.minimum(w5.n_steps, eval_steps)
+        launch = tune_batched(P, torch, w5)
         if log:
-            log(f"bench: batched {mode}: {out[mode]}")
-    net.close()
+            log(f"bench: batched launch shape {launch}")
+        out = {"instances": int(w5.batch), "steps_per_instance": [int(ns.min()), int(ns.max())],
+               "train_rows": int(raw.shape[0]), "collect_s": t_collect, "train_s": t_train,
+               "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-50:].mean()),
+               "skip_sigma": float(net.get_skip()[1]), "launch": launch}
+        del raw
+        ref = None
+        for mode in ("zero", "prev", "skip", "mlp"):
+            fin, st, el = learned.propagate(torch, op, w5.pulses, ns, w5.psi0, w5.dt, mode, net=net,
+                                            wg_per_cu=launch["wg_per_cu"])
+            act = learned.active_mask(ns, st.shape[0])
+            if ref is None:
+                ref = fin
+            d = float(torch.linalg.vector_norm(fin - ref).item() / torch.linalg.vector_norm(ref).item())
+            out[mode] = {"iters_per_step": float(st["iters"][act].mean()),
+                         "instance_steps_per_s": float(act.sum() / el),
+                         "batched_steps_per_s": float(st.shape[0] / el),
+                         "all_converged": bool(np.all(st["status"][act] == 0)), "rel_diff_vs_zero_guess": d}
+            if log:
+                log(f"bench: batched {mode}: {out[mode]}")
+            del fin
+        del ref
+    finally:
+        net.close()
     return out
 
 
-def spmv_measure(P, torch, w, reps=20):
-    """Standalone operator apply y = S x + i dt/2 H x: average kernel time (HIP events)."""
+def apply_section(P, torch, w, reps=20):
+    """Standalone operator apply y = S x + i dt/2 H x at the step's fields: average kernel time
+    (HIP events on the library's stream), algorithmic GB/s and GFLOP/s."""
+    from oracle.fields import field_values, midpoint_time
     s = P.Solver(w.op, w.batch)
-    s.set_field(np.ones((w.batch, w.op.n_fields)) * 0.01)
-    x = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
-    y = torch.empty_like(x)
-    stream = torch.cuda.current_stream()
-    for _ in range(3):
-        s.apply(x, y, 1.0, 0.5j * w.dt)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
+    try:
+        s.set_field(np.array([field_values(w.pulses[0], midpoint_time(w.t0, w.dt))]))
+        x = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
+        y = torch.empty_like(x)
+        stream = torch.cuda.current_stream()
+        for _ in range(3):
+            s.apply(x, y, 1.0, 0.5j * w.dt)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            s.apply(x, y, 1.0, 0.5j * w.dt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        del x, y
+    finally:
+        s.close()
+    b = apply_bytes(w.op)
+    fl = apply_flops(w.op)
+    return {"kernel": "apply_kernel<double>", "ms": ms, "alg_bytes": b, "alg_GBps": b / (ms * 1e-3) / 1e9,
+            "frac_hbm": b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "alg_flop": fl,
+            "GFLOPs": fl / (ms * 1e-3) / 1e9, "frac_fp64": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
+
+
+# ------------------------------------------------------------------------------ CPU oracle baseline
+
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"os_cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline_extrapolated(w, matvecs, precs, iters, n_channels=4):
+    """The oracle's step cost on the host, extrapolated from timed pieces (the assembled operator of
+    this workload does not fit in host memory): the CSR matvec of a row slice of n_channels channels
+    (scaled by nang / n_channels), one channel block's sparse-LU preconditioner solve (scaled by the
+    channel count) and one vector update over all unknowns (scaled by the step's vector passes),
+    combined with the GPU run's matvecs, preconditioner solves and iterations per step."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+
+    from oracle.assemble import channel_rows, kappa_poly_block
+    from oracle.fields import field_values, midpoint_time
+    op = w.op
+    f = field_values(w.pulses[0], midpoint_time(w.t0, w.dt))
+    j0 = op.nang // 2
+    t_build = time.perf_counter()
+    rows = channel_rows(op, f, 1.0, 0.5j * w.dt, j0, j0 + n_channels)
+    t_build = time.perf_counter() - t_build
+    x = w.psi0.reshape(-1)
+    reps = 3
+    t0 = time.perf_counter()
     for _ in range(reps):
-        s.apply(x, y, 1.0, 0.5j * w.dt)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    s.close()
-    return ms
+        rows @ x
+    t_mv = (time.perf_counter() - t0) / reps * op.nang / n_channels
+    kap = float(op.kappa[j0])
+    blk = kappa_poly_block(op.h_poly, kap, op.nr, op.hb).astype(np.complex128)
+    sblk = kappa_poly_block(op.s_poly, kap, op.nr, op.hb) if op.s_poly.shape[0] else sp.identity(2 * op.nr)
+    M = (sblk + 0.5j * w.dt * blk).tocsc()
+    lu = spla.splu(M)
+    v = x[:2 * op.nr].copy()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lu.solve(v)
+    t_pc = (time.perf_counter() - t0) / reps * op.nang
+    y = np.empty_like(x)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        np.add(x, 0.3 * x, out=y)
+    t_vec = (time.perf_counter() - t0) / reps
+    t_step = matvecs * t_mv + precs * t_pc + (4 + 12 * iters) * t_vec
+    info = host_info()
+    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"extrapolated: CSR matvec of the rows of {n_channels} of {op.nang} channels "
+                       f"({rows.nnz} nonzeros, {t_mv / op.nang * n_channels * 1e3:.1f} ms, x {op.nang / n_channels:.1f}), "
+                       f"one channel block's sparse-LU solve (x {op.nang}), one vector update (x "
+                       f"{4 + 12 * iters:.0f}); combined with the GPU run's {matvecs:.2f} matvecs, "
+                       f"{precs:.2f} preconditioner solves, {iters:.2f} iterations per step; "
+                       f"scipy CSR matvec and SuperLU solve are single-threaded"),
+            "s_per_matvec": t_mv, "s_per_precond": t_pc, "s_per_vector_pass": t_vec, "s_per_step": t_step,
+            "slice_assembly_s": t_build, **info}
 
 
-def cpu_baseline(w, precond, budget_s=20.0):
-    """The oracle (CSR assembly once, preconditioned textbook BiCGSTAB per step) on the host cores.
-    Returns (steps/s, steps, seconds, threads used = process CPU time / wall time)."""
+def cpu_baseline_steps(w, precond, budget_s=20.0):
+    """The oracle (CSR assembly once, preconditioned textbook BiCGSTAB per step) on the host cores,
+    whole steps of the same workload. Returns (steps/s, steps, seconds, threads used)."""
     from oracle.assemble import Assembled
     from oracle.step import BlockPreconditioner, cn_step
     asm = Assembled(w.op)
@@ -303,58 +460,53 @@ def cpu_baseline(w, precond, budget_s=20.0):
     return n / el, n, el, max(1, round(cpu / el))
 
 
+# ------------------------------------------------------------------------------ main
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the beyond-dipole apply measurement")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched learned-guess comparison")
-    ap.add_argument("--batched-steps", type=int, default=200, help="steps per instance in the batched sections")
-    ap.add_argument("--wg-per-cu", default="auto",
-                    help="persistent work-groups per CU (1..4), or 'auto' to autotune before the warmup")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--sections", default=",".join(SECTIONS),
+                    help="comma list of sub-lines to run beside the headline: " + ",".join(SECTIONS) + " (or none)")
+    ap.add_argument("--sub-steps", type=int, default=200, help="steps of the hydrogen / small-case sub-lines")
+    ap.add_argument("--batched-steps", type=int, default=200, help="steps per instance in the batched section")
+    ap.add_argument("--wg-per-cu", default="0", help="persistent work-groups per CU (1..4, 0 = default), or auto")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB once (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this build runs on one GPU; runs on several GPUs are not part of it",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    sections = set() if args.sections in ("", "none") else set(args.sections.split(","))
 
     import torch
 
     import paper_2512_21697_amd as P
     from workloads import dkb, synthetic
 
-    _log("bench: building hydrogen workload (Nr=2000, 41 channels)")
-    w = dkb.config2()
-    E = w.op.n_unknowns
-    _log(f"bench: gpu steps={args.steps} warmup={args.warmup}")
+    _log("bench: building the beyond-dipole workload (Nr=4000, 770 channels, six terms, N=6.16e6)")
+    w3 = synthetic.config3(driven=True)
     launch = args.wg_per_cu if args.wg_per_cu == "auto" else int(args.wg_per_cu)
     tuning = {}
-    ms_step, st, launches, wall, psi64 = run_gpu_steps(P, torch, w, args.steps, args.warmup, precond=1,
-                                                       guess=P.GUESS_PREV, launch=launch, info=tuning)
-    _log(f"bench: launch shape {tuning}")
-    iters = st["iters"].astype(float)
-    mv = st["matvecs"].astype(float)
-    ok = bool(np.all(st["status"] == 0))
-    # roofline of the persistent solver kernel (the only kernel of the timed region)
-    kern_ms = sum(t for t, _ in launches) / max(1, len(launches))
-    steps_per_launch = sum(n for _, n in launches) / max(1, len(launches))
-    it_mean = float(iters.mean())
-    bytes_step = algorithmic_bytes_per_step(w.op, float(mv.mean()), float(st["precs"].mean()), it_mean)
-    achieved = bytes_step * steps_per_launch / (kern_ms * 1e-3) / 1e9
-    tr = measured_traffic(tuning.get("wg_per_cu"))
+    _log(f"bench: gpu steps={args.steps} warmup={args.warmup}")
+    ms_step, st, launches, wall, psi = run_gpu_steps(P, torch, w3, args.steps, args.warmup, precond=1,
+                                                     guess=P.GUESS_PREV, launch=launch, info=tuning)
+    del psi
+    head = step_summary(w3, ms_step, st, launches)
+    _log(f"bench: headline {head}")
+    key = f"wg{tuning.get('wg_per_cu')}"
+    tr = measured_traffic("beyond_dipole", key)
     traffic = None
+    passes = None
     if tr is not None:
-        traffic = (tr["fetch_kib_per_step"] * tr["fetch_scale"] + tr["write_kib_per_step"] * tr["write_scale"]) * 1024.0 \
-            * steps_per_launch
+        per_step = (tr["fetch_kib_per_step"] * tr["fetch_scale"] + tr["write_kib_per_step"] * tr["write_scale"]) * 1024.0
+        traffic = per_step * head["steps_per_launch"]
+        passes = per_step / max(1.0, head["iters_per_step"]) / (w3.op.n_unknowns * 16)
     res = {
-        "metric": "TDDE steps/s (hydrogen dipole, preconditioned FP64 BiCGSTAB to 1e-12)",
-        "value": 1000.0 / ms_step,
+        "metric": "TDDE steps/s (beyond-dipole operator, preconditioned FP64 BiCGSTAB to 1e-12)",
+        "value": head["steps_per_s"],
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -364,45 +516,60 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c128",
-        "data": "synthetic (seeded generator; DKB hydrogen operator computed on the host)",
-        "config": {"workload": "hydrogen dipole: Nr=2000, Nang=41 (l<=20, mu=1/2), N=164000, dt=2e-4, "
-                               "E0=0.05, w=0.057, 8-cycle sin^2, ground-state start, tol 1e-12, "
+        "data": "synthetic (seeded generator of the beyond-dipole recipe; no dataset)",
+        "config": {"workload": "beyond-dipole single-GPU share: Nr=4000 (order 7), Nang=770 (l<=40, |mu|<=9/2), "
+                               "six coupling terms |dl|<=2 mu'=mu+-1, N=6.16e6 complex128, dt=1e-3, "
+                               "E0=0.05 sin^2 pulses at w=0.057 and w+-2pi/T (T=20) from t=T/4, tol 1e-12, "
                                "block-LU preconditioner, previous-state guess",
                    "batch": 1, "seq_len": None, "parallelism": "single GPU", "launch": tuning},
-        "iters_per_step": it_mean,
-        "matvecs_per_step": float(mv.mean()),
-        "precond_solves_per_step": float(st["precs"].mean()),
-        "all_converged": ok,
-        "max_true_rel_res": float(st["true_rel_res"].max()),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "persistent_kernel", "kernel_ms_per_launch": kern_ms,
-                     "steps_per_launch": steps_per_launch, "alg_bytes_per_launch": bytes_step * steps_per_launch,
-                     "alg_bytes_per_step": bytes_step, "source_hash": source_hash()},
+        "iters_per_step": head["iters_per_step"],
+        "matvecs_per_step": head["matvecs_per_step"],
+        "precond_solves_per_step": head["precond_solves_per_step"],
+        "all_converged": head["all_converged"],
+        "max_true_rel_res": head["max_true_rel_res"],
+        "roofline": {"bound": "hbm", "achieved": head["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "persistent_kernel", "kernel_ms_per_launch": head["kernel_ms_per_launch"],
+                     "steps_per_launch": head["steps_per_launch"],
+                     "alg_bytes_per_launch": head["alg_bytes_per_step"] * head["steps_per_launch"],
+                     "alg_bytes_per_step": head["alg_bytes_per_step"],
+                     "hbm_passes_per_iteration": passes, "source_hash": source_hash()},
     }
-    if not args.no_mixed:
-        _log("bench: mixed precision on the hydrogen operator")
-        res["mixed_precision"] = mixed_section(P, torch, w, args.steps, args.warmup, psi64)
-    if not args.no_batched:
+    sub = {}
+    if "c3plain" in sections:
+        _log("bench: beyond-dipole without preconditioner")
+        sub["beyond_dipole_plain"] = step_section(P, torch, w3, args.steps, args.warmup, 0, label="c3 driven, no M")
+    if "apply" in sections:
+        _log("bench: beyond-dipole standalone apply")
+        sub["beyond_dipole_apply"] = apply_section(P, torch, w3)
+    if "c2" in sections or "c2d" in sections or "mixed" in sections:
+        _log("bench: building the hydrogen workload (Nr=2000, 41 channels)")
+        w2 = dkb.config2()
+        if "c2" in sections:
+            sub["hydrogen"] = step_section(P, torch, w2, args.sub_steps, 5, 1, label="hydrogen from the ground state, t=0")
+        if "c2d" in sections:
+            w2d = dkb.config2(E0=0.5, driven=True)
+            sub["hydrogen_driven"] = step_section(P, torch, w2d, args.sub_steps, 5, 1,
+                                                  label="hydrogen mid-pulse t=T/2+pi/(2w), E0=0.5")
+            del w2d
+        if "mixed" in sections:
+            _log("bench: mixed precision on the hydrogen operator")
+            sub["mixed_precision"] = mixed_section(P, torch, w2, args.sub_steps, 5)
+        del w2
+    if "c1" in sections:
+        for drv in (False, True):
+            w1 = synthetic.config1(driven=drv)
+            for g, gn in ((P.GUESS_PREV, "prev"), (P.GUESS_ZERO, "zero")):
+                sub[f"small_{'driven_' if drv else ''}{gn}"] = step_section(
+                    P, torch, w1, 20, 5, 0, guess=g, label=f"N=3200 {'t0=T/4' if drv else 't0=0'}")
+    if "batched" in sections:
         _log("bench: batched sweep, learned vs plain guesses")
-        res["batched_learned"] = batched_learned_section(P, torch, args.batched_steps, args.batched_steps, log=_log)
-    if not args.no_extra:
-        _log("bench: beyond-dipole apply (Nr=4000, Nang=770, N=6.16e6)")
-        w3 = synthetic.config3()
-        ms3 = spmv_measure(P, torch, w3)
-        E3 = w3.op.n_unknowns
-        b3 = apply_bytes(w3.op)
-        res["spmv_beyond_dipole"] = {"ms": ms3, "alg_GBps": b3 / (ms3 * 1e-3) / 1e9,
-                                     "frac_hbm": b3 / (ms3 * 1e-3) / 1e9 / HBM_PEAK_GBS, "alg_bytes": b3,
-                                     "N": E3}
-        del w3
-    if not args.no_cpu:
-        _log("bench: cpu oracle baseline")
-        rate, n, el, threads = cpu_baseline(w, True, args.cpu_budget)
-        res["cpu_baseline"] = {"value": rate, "unit": "steps/s", "cores": threads, "kind": "oracle",
-                               "sample": f"{n} steps of the same workload from the ground state "
-                                         f"({el:.1f} s; CSR assembly and LU factorisation excluded; "
-                                         f"cores = process CPU time / wall time)"}
+        sub["batched_learned"] = batched_learned_section(P, torch, args.batched_steps, args.batched_steps, log=_log)
+    res["sub"] = sub
+    if "cpu" in sections:
+        _log("bench: cpu oracle baseline (extrapolated from timed pieces)")
+        res["cpu_baseline"] = cpu_baseline_extrapolated(w3, head["matvecs_per_step"], head["precond_solves_per_step"],
+                                                        head["iters_per_step"])
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 16
         a = torch.ones(n, dtype=torch.complex128, device="cuda:0")
@@ -411,7 +578,15 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         res["copy_probe_bytes"] = 2 * n * 16
-    print(json.dumps(res))
+        del a, b
+    # Release every device buffer before the interpreter exits: library contexts are closed where
+    # they are used; drop the remaining tensors and the caching allocator's blocks while the HIP
+    # runtime is still up (finalisers that free device memory after a profiler's own exit-time
+    # teardown have crashed the process).
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

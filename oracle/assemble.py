@@ -86,3 +86,33 @@ class Assembled:
     def operator(self, fvals, a_s: complex, a_h: complex) -> sp.csr_matrix:
         """a_S S + a_H H(t)."""
         return (a_s * self.S + a_h * self.hamiltonian(fvals)).tocsr()
+
+
+def channel_rows(op, fvals, a_s: complex, a_h: complex, j0: int, j1: int) -> sp.csr_matrix:
+    """Rows of channels [j0, j1) of a_S S + a_H H(t): the same construction as the full assembly
+    (eq. fullH), restricted to those block rows, as a ((j1-j0) 2nr) x (nang 2nr) CSR matrix. Used
+    where the whole matrix does not fit in memory (sampled parity, timing of a row slice)."""
+    nr, hb, nang = op.nr, op.hb, op.nang
+    n = 2 * nr
+    blocks = []
+    for j in range(j0, j1):
+        b = kappa_poly_block(op.h_poly, float(op.kappa[j]), nr, hb).astype(np.complex128)
+        if op.h_chan is not None:
+            b = b + radial_2x2(op.h_chan[j], nr, hb)
+        if op.s_poly.shape[0] == 0:
+            sb = sp.identity(n, dtype=np.complex128, format="csr")
+        else:
+            sb = kappa_poly_block(op.s_poly, float(op.kappa[j]), nr, hb).astype(np.complex128)
+        blocks.append(a_s * sb + a_h * b)
+    diag = sp.block_diag(blocks, format="csr")
+    left = sp.csr_matrix(((j1 - j0) * n, j0 * n), dtype=np.complex128)
+    right = sp.csr_matrix(((j1 - j0) * n, (nang - j1) * n), dtype=np.complex128)
+    out = sp.hstack([left, diag, right], format="csr")
+    for t in op.terms:
+        scale = a_h * t.coef * fvals[t.field]
+        if scale == 0:
+            continue
+        a = sp.csr_matrix((t.a_val, t.a_col, t.a_rowptr), shape=(nang, nang))
+        ang = (sp.diags(op.kappa ** t.kpow[0]) @ a @ sp.diags(op.kappa ** t.kpow[1])).tocsr()[j0:j1]
+        out = out + scale * sp.kron(ang, radial_2x2(t.r_band, nr, hb), format="csr")
+    return out.tocsr()
