@@ -27,9 +27,9 @@
  *   - Every function returns a tdde_status; nothing throws across the ABI. On error the
  *     context stays usable and tdde_last_error() describes the failure.
  *   - Memory: tdde_assemble allocates every device buffer the context needs (operator copy,
- *     Krylov workspace, preconditioner factors, reduction scratch). tdde_set_dt,
- *     tdde_set_pulses, tdde_set_field, tdde_apply, tdde_solve, tdde_step, tdde_run_batched
- *     allocate nothing.
+ *     Krylov workspace, reduction scratch); tdde_set_dt the preconditioner factors on its first
+ *     call. tdde_set_pulses, tdde_set_field, tdde_apply, tdde_solve, tdde_step,
+ *     tdde_run_batched allocate nothing.
  */
 #ifndef TDDE_H
 #define TDDE_H
@@ -44,6 +44,8 @@ typedef enum {
   TDDE_OK = 0,
   TDDE_NOT_CONVERGED = 1, /* max_iter reached; x holds the last iterate, stats are filled      */
   TDDE_BREAKDOWN = 2,     /* repeated BiCGSTAB breakdown (rho or omega vanished after restart)  */
+  TDDE_NONFINITE = 3,     /* NaN or Inf in the right-hand side, guess or iteration; the solve    */
+                          /* stopped at the first reduction that saw it (x: the last iterate)    */
   TDDE_ERR_ARG = -1,      /* bad argument or shape; nothing was launched                        */
   TDDE_ERR_HIP = -2,      /* a HIP call failed; message in tdde_last_error                      */
   TDDE_ERR_NOMEM = -3,    /* device allocation failed in tdde_assemble                          */
@@ -123,52 +125,68 @@ typedef struct {
 } tdde_solve_stats;
 
 /* Create a context for the given sizes on `hip_stream` (hipStream_t or NULL). Allocates nothing
- * on the device. Errors: TDDE_ERR_ARG for nonpositive sizes, half_band != 6 or n_fields > 16. */
+ * on the device. Errors: TDDE_ERR_ARG for nonpositive sizes, half_band != 6 or n_fields > 16.
+ * Paper: the per-rank set-up before the time loop (Sec. 3.1, the implementation steps). */
 tdde_status tdde_create(const tdde_dims* dims, void* hip_stream, tdde_ctx** out);
 
 /* Copy the operator to the device (FP64 and FP32 copies) and allocate every workspace buffer.
  * May be called once per context. Errors: TDDE_ERR_ARG (inconsistent CSR, kappa exponents with
- * zero kappa, field index out of range), TDDE_ERR_NOMEM, TDDE_ERR_HIP. */
+ * zero kappa, field index out of range), TDDE_ERR_NOMEM, TDDE_ERR_HIP.
+ * Paper: the operator of eq. fullH (h and g sub-matrices, the angular coupling H^theta) copied to
+ * the device once and memory allocated once before the time loop (Sec. 3.1, steps 2 and 5). */
 tdde_status tdde_assemble(tdde_ctx* ctx, const tdde_operator_desc* desc);
 
 /* Set the time step. Factors M = S + i dt/2 H0 per distinct channel block (banded LU without
  * pivoting, valid because the Hermitian part of M is the SPD overlap S) and uploads the
- * factors. Must follow tdde_assemble. */
+ * factors. Must follow tdde_assemble. Allocates the factor buffers on its first call.
+ * Paper: the preconditioner of eq. matrixM, factored once at start-up (Sec. 2.4; Sec. 3.1 step 4). */
 tdde_status tdde_set_dt(tdde_ctx* ctx, double dt);
 
 /* Pulses of every instance: host array [batch][n_fields]. Used by tdde_step / tdde_run_batched,
- * which evaluate f at the midpoint time of each step on the device. */
+ * which evaluate f at the midpoint time of each step on the device (this replaces a field table
+ * set with tdde_set_field_table). Paper: the sin^2-envelope time functions of eq. ndpPot and
+ * eq. bdpA, evaluated at the midpoint t + dt/2 of Sec. 2.4. */
 tdde_status tdde_set_pulses(tdde_ctx* ctx, const tdde_pulse* pulses);
 
-/* Explicit field values f[batch][n_fields] (host) used by tdde_apply and tdde_solve. */
+/* Explicit field values f[batch][n_fields] (host) used by tdde_apply and tdde_solve.
+ * Paper: the scalar time functions f_alpha(t) that multiply the coupling terms
+ * of eq. fullH (computing H(t) for a step, Sec. 3.1 step 2a). */
 tdde_status tdde_set_field(tdde_ctx* ctx, const double* f);
 
 /* y = a_s * S x + a_h * H x for every instance, with the fields of tdde_set_field.
- * x, y: device [batch][nang][2][nr] complex128, x != y. */
+ * x, y: device [batch][nang][2][nr] complex128, x != y. No synchronisation.
+ * Paper: the product H x of eq. fullH (the SpMV of Sec. 3.3, here matrix-free). */
 tdde_status tdde_apply(tdde_ctx* ctx, tdde_c128 a_s, tdde_c128 a_h, const void* x_dev, void* y_dev);
 
-/* Same in complex64 with the FP32 operator copy (FP32 accumulation). */
+/* Same in complex64 with the FP32 operator copy (FP32 accumulation): the inner apply of the mixed
+ * precision solve (an addition to the paper's FP64 method, Sec. 4 reports FP64 complex only). */
 tdde_status tdde_apply_c64(tdde_ctx* ctx, tdde_c128 a_s, tdde_c128 a_h, const void* x_dev, void* y_dev);
 
-/* Apply the block preconditioner: z = M^-1 v (complex128, device). Needs tdde_set_dt. */
+/* Apply the block preconditioner: z = M^-1 v (complex128, device, [batch][nang][2][nr]).
+ * Needs tdde_set_dt. Paper: the LU solve with the factors of eq. matrixM (Sec. 2.4). */
 tdde_status tdde_precond_apply(tdde_ctx* ctx, const void* v_dev, void* z_dev);
 
 /* Solve (S + i dt/2 H) x = b with the fields of tdde_set_field. b, x: device complex128
  * [batch][nang][2][nr]; x holds the initial guess on entry (opts->guess must be GIVEN or ZERO)
  * and the solution on exit. stats: host array [batch] or NULL (NULL = no synchronisation).
- * Returns TDDE_NOT_CONVERGED / TDDE_BREAKDOWN when any instance did not converge. */
+ * Returns TDDE_NOT_CONVERGED / TDDE_BREAKDOWN when any instance did not converge.
+ * Paper: the BiCGSTAB solve of the Crank-Nicolson system eq. solPsi (Sec. 2.4, Sec. 3.1 step 2b). */
 tdde_status tdde_solve(tdde_ctx* ctx, const void* b_dev, void* x_dev, const tdde_solve_opts* opts,
                        tdde_solve_stats* stats);
 
-/* One time step of every instance from time t: evaluates f_m(t + dt/2) from the pulses, forms
- * b = (S - i dt/2 H) psi, solves with BiCGSTAB from the chosen guess, writes psi_{n+1} into psi.
- * guess_dev: device complex128 guess when opts->guess == GIVEN, else ignored (may be NULL).
- * stats: host [batch] or NULL. */
+
+/* One time step of every instance from time t: evaluates f_m(t + dt/2) from the pulses (or takes
+ * row 0 of the field table), forms b = (S - i dt/2 H) psi, solves with BiCGSTAB from the chosen
+ * guess, writes psi_{n+1} into psi. guess_dev: device complex128 guess when opts->guess == GIVEN,
+ * else ignored (may be NULL). stats: host [batch] or NULL.
+ * Paper: one step of the time loop, eq. solPsi with the midpoint rule (Sec. 2.4, Sec. 3.1 step 2). */
 tdde_status tdde_step(tdde_ctx* ctx, void* psi_dev, double t, const void* guess_dev, const tdde_solve_opts* opts,
                       tdde_solve_stats* stats);
 
 /* Advance every instance by up to n_chunk steps in one persistent launch. Instance b advances
  * from step index step0 while step < n_steps[b] (host array [batch]); time t = t0 + step * dt.
+ * Paper: the time loop of Sec. 3.1 step 2 run fully on the device (Sec. 3.3), for a batch of
+ * independent instances that share the operator (an addition to the paper: different fields).
  * guess_dev: device complex128 [batch][E] initial guess, required when opts->guess == GIVEN (then
  * n_chunk must be 1), else ignored. stats_dev: device array [n_chunk][batch] of tdde_solve_stats,
  * or NULL. No host synchronisation. */
@@ -191,12 +209,21 @@ tdde_status tdde_set_launch(tdde_ctx* ctx, int32_t wg_per_cu);
 /* Persistent-grid size actually used (work-groups) and the per-instance work-group count. */
 tdde_status tdde_launch_info(tdde_ctx* ctx, int32_t* n_wg, int32_t* wg_per_instance);
 
-/* Diagnostics: record up to cap phase timestamps of work-group 0 in every later persistent launch
+/* Diagnostics (no passage of the paper: measurement support, Sec. 4 reports wall times per step):
+ * record up to cap phase timestamps of work-group 0 in every later persistent launch
  * (value = (wall_clock64 << 8) | phase id; the device wall clock runs at 100 MHz on gfx950).
  * cap = 0 disables. tdde_debug_read_marks synchronises the stream and copies them to the host. */
 tdde_status tdde_debug_phase_marks(tdde_ctx* ctx, int32_t cap);
 tdde_status tdde_debug_read_marks(tdde_ctx* ctx, uint64_t* host, int32_t cap);
 
+/* Test hook (no passage of the paper: it drives the breakdown branch of the iteration): shadow
+ * residual r^ of the first BiCGSTAB cycle of every later tdde_solve, a device
+ * complex128 array [batch][nang][2][nr] that must stay valid while those calls run (NULL restores
+ * r^ = r0). A shadow with <r^, r0> = 0 makes rho vanish at once, and the solve restarts with
+ * r^ = r; steps (tdde_step, tdde_run_batched) always take r^ = r0. */
+tdde_status tdde_debug_set_shadow(tdde_ctx* ctx, const void* shadow_dev);
+
+/* Error reporting of the ABI (no passage of the paper): text of a status / of the context's last error. */
 const char* tdde_status_string(tdde_status s);
 const char* tdde_last_error(const tdde_ctx* ctx); /* NULL ctx: last create error */
 

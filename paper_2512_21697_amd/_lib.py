@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtdde.so")
 
-TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN = 0, 1, 2
+TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN, TDDE_NONFINITE = 0, 1, 2, 3
 GUESS_ZERO, GUESS_PREV, GUESS_GIVEN = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 
@@ -60,7 +60,7 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"),
 EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field", "tdde_apply",
            "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_step", "tdde_run_batched", "tdde_destroy",
            "tdde_launch_info", "tdde_set_launch", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
-           "tdde_debug_read_marks", "tdde_mlp_create", "tdde_mlp_destroy",
+           "tdde_debug_read_marks", "tdde_debug_set_shadow", "tdde_mlp_create", "tdde_mlp_destroy",
            "tdde_mlp_param_count", "tdde_mlp_set_params", "tdde_mlp_get_params", "tdde_mlp_get_grads",
            "tdde_mlp_forward", "tdde_mlp_backward", "tdde_mlp_adam", "tdde_mlp_set_pulses", "tdde_mlp_guess",
            "tdde_mlp_last_error", "tdde_mlp_fit_skip", "tdde_mlp_set_skip", "tdde_mlp_get_skip"]
@@ -94,6 +94,7 @@ def load():
         "tdde_set_launch": [P, C.c_int32],
         "tdde_debug_phase_marks": [P, C.c_int32],
         "tdde_debug_read_marks": [P, P, C.c_int32],
+        "tdde_debug_set_shadow": [P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -279,9 +280,9 @@ class Solver:
     def solve(self, b, x, opts, stats=True):
         out = (SolveStats * self.batch)() if stats else None
         n = self.batch * self.E
-        st = self._check(self.lib.tdde_solve(self.h, _buf(b, n), _buf(x, n), C.byref(opts),
-                                             C.cast(out, C.c_void_p) if stats else None),
-                         allow=(TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN))
+        fn = self.lib.tdde_solve
+        st = self._check(fn(self.h, _buf(b, n), _buf(x, n), C.byref(opts), C.cast(out, C.c_void_p) if stats else None),
+                         allow=(TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN, TDDE_NONFINITE))
         return st, ([s.as_dict() for s in out] if stats else None)
 
     def step(self, psi, t, opts, guess=None, stats=True):
@@ -290,7 +291,7 @@ class Solver:
         g = _buf(guess, n) if guess is not None else None
         st = self._check(self.lib.tdde_step(self.h, _buf(psi, n), float(t), g, C.byref(opts),
                                             C.cast(out, C.c_void_p) if stats else None),
-                         allow=(TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN))
+                         allow=(TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN, TDDE_NONFINITE))
         return st, ([s.as_dict() for s in out] if stats else None)
 
     def run_batched(self, psi, t0, step0, n_chunk, n_steps, opts, stats_dev=None, guess=None):
@@ -306,6 +307,13 @@ class Solver:
         self._check(self.lib.tdde_run_batched(self.h, _buf(psi, self.batch * self.E), float(t0), int(step0),
                                               int(n_chunk), ns.ctypes.data_as(C.c_void_p), g, C.byref(opts),
                                               _ptr(stats_dev)))
+
+    def set_shadow(self, shadow):
+        """Test hook: shadow residual of the first BiCGSTAB cycle of later solves (None: r^ = r0).
+        The tensor must stay alive while those solves run."""
+        self._shadow = shadow
+        p = None if shadow is None else _buf(shadow, self.batch * self.E)
+        self._check(self.lib.tdde_debug_set_shadow(self.h, p))
 
     def enable_marks(self, cap):
         self._check(self.lib.tdde_debug_phase_marks(self.h, int(cap)))

@@ -13,7 +13,9 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtdde.so")
-SOURCES = ["tdde.hip", "mlp.hip"]
+# (source, extra flags, object name): the persistent solver is compiled once per variant
+SOURCES = [("tdde.hip", [], "tdde"), ("mlp.hip", [], "mlp")] + [
+    ("persistent.hip", [f"-DTDDE_VARIANT={v}"], f"persistent_v{v}") for v in range(4)]
 ARCH = os.environ.get("TDDE_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -25,13 +27,13 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     inc = ["-I", os.path.join(HERE, "..", "include")]
     with tempfile.TemporaryDirectory(prefix="tdde_build_") as tmpd:
         objs, procs = [], []
-        for src in srcs:
-            obj = os.path.join(tmpd, os.path.basename(src) + ".o")
-            cmd = ["hipcc", *FLAGS, *inc, "-c", "-o", obj, src]
+        for name, extra, oname in SOURCES:
+            src = os.path.join(CSRC, name)
+            obj = os.path.join(tmpd, oname + ".o")
+            cmd = ["hipcc", *FLAGS, *extra, *inc, "-c", "-o", obj, src]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))

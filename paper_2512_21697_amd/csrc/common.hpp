@@ -7,13 +7,16 @@
 namespace tdde {
 
 constexpr int kThreads = 256;    // work-group size of every kernel
-constexpr int kTileR = 128;      // radial points per tile (x 2 spinor components = 256 threads)
 constexpr int kHB = 6;           // radial half-bandwidth: order-7 B-splines overlap 6 neighbours per side
 constexpr int kMaxHB = kHB;
+// A tile is one channel over kStage staged radial points per spinor component (2 x kStage = 256
+// threads, one staged point each); its kTileR = kStage - 2 hb inner points are the outputs, the
+// hb points on either side the halo of the radial band.
+constexpr int kStage = kThreads / 2;
+constexpr int kTileR = kStage - 2 * kHB;
 constexpr int kMaxTerms = 32;    // largest number of coupling terms
 constexpr int kMaxGroup = 8;     // coupling terms staged together (one group: union angular pattern)
 constexpr int kMaxFields = 16;   // largest number of time functions per instance
-constexpr int kHalo = kTileR + 2 * kMaxHB;
 
 template <typename T> struct cvec;
 template <> struct cvec<double> { using type = double2; };
@@ -79,7 +82,7 @@ template <typename T> struct DevOp {
   int n_h, n_s, has_chan;
   int pq_h, pq_s, pq_chan;     // 1 when the blocks couple s != s'
   int n_terms;
-  int n_itiles;                // ceil(nr / kTileR)
+  int n_itiles;                // ceil(nr / kTileR) radial tiles per channel
   // H0 and S of every distinct kappa, the kappa polynomials summed on the host:
   // h_blk[kb][s][s'][d][i] = sum_n kappa^n h_n[s][s'][d][i] (likewise s_blk), kb = kblk_of[j]
   const int* kblk_of;          // [nang]
@@ -103,6 +106,27 @@ template <typename T> struct DevOp {
   const int* t_field;          // [n_terms]
   const double2* t_coef;       // [n_terms] (double even for the FP32 copy)
 };
+
+// Tile t of one instance -> (channel j, radial tile it). The work-group that takes tile t is
+// t mod G (G a multiple of 8, or the tile index itself in the standalone apply) and work-groups are
+// dispatched round-robin over the 8 XCDs, so tile t runs on XCD t % 8. The first 8 floor(nit / 8)
+// radial tiles are dealt in groups of 8 with the radial tile fastest: radial tile it of every
+// channel runs on XCD it % 8, channel after channel, so the x tiles that the angular coupling of
+// neighbouring channels reads again are in that XCD's L2. The remaining radial tiles follow,
+// channel-major.
+__device__ inline void tile_coords(int nang, int nit, int t, int& j, int& it) {
+  const int n8 = nit & ~7;
+  const int full = n8 * nang;
+  if (t < full) {
+    const int q = t / (8 * nang), r = t - q * 8 * nang;
+    j = r >> 3;
+    it = q * 8 + (r & 7);
+  } else {
+    const int rem = t - full, nl = nit - n8;
+    j = rem / nl;
+    it = n8 + (rem - j * nl);
+  }
+}
 
 // Sum over the work-group of a complex (two doubles), fixed order: wave shuffles, then waves in
 // order. lds holds 2 * kThreads / 64 doubles.

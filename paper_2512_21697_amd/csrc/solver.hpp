@@ -30,7 +30,11 @@ namespace tdde {
 // ST_VERIFY: the true residual b - A x is formed in the next window; ST_VCHECK: it is tested in the
 // window after that (accept, or restart from it as ST_PENDING, which the next W0 picks up).
 enum { ST_INACTIVE = 0, ST_ACTIVE = 1, ST_VERIFY = 2, ST_DONE = 3, ST_FAILED = 4, ST_PENDING = 5, ST_BREAKDOWN = 6,
-       ST_VCHECK = 7 };
+       ST_VCHECK = 7, ST_NONFINITE = 8 };
+// Status reported for a final state (the ABI's tdde_status values).
+__device__ inline int status_of(int state) {
+  return state == ST_DONE ? 0 : (state == ST_BREAKDOWN ? 2 : (state == ST_NONFINITE ? 3 : 1));
+}
 // A slot is never read and written in the same barrier window by one instance.
 //   RHO, RR: written W4, read W0; RR also written by a residual check and read in the window after it
 //   AUX: ||r||^2 of a restart, written by a restart or a non-fused residual check, read W0 when PENDING
@@ -73,6 +77,7 @@ struct SolveArgs {
   double2* psi;           // MODE_STEP state (in/out)
   const double2* guess_in;
   const double2* b_in;    // MODE_SOLVE right-hand side
+  const double2* shadow;  // MODE_SOLVE: shadow residual r^ of the first cycle (null: r^ = r)
   double2* x_io;          // MODE_SOLVE solution (in: guess)
   double2* part;          // [B][G][kSlots]
   unsigned* bar;          // grid barrier state
@@ -166,16 +171,15 @@ template <typename T> __device__ inline SharedLds<T>& lds_of(Shared& sh);
 template <> __device__ inline SharedLds<double>& lds_of<double>(Shared& sh) { return sh.u.d; }
 template <> __device__ inline SharedLds<float>& lds_of<float>(Shared& sh) { return sh.u.f; }
 
-// Tile loop of the calling work-group over its instance (radial tile fastest).
-#define FOR_TILES(op, wi)                                                          \
-  for (int tile_ = (wi).g; tile_ < (op).nang * (op).n_itiles; tile_ += (wi).G)     \
-    for (int j_ = tile_ / (op).n_itiles, once_ = 1; once_; once_ = 0)             \
-      for (int i0_ = (tile_ - j_ * (op).n_itiles) * kTileR, once2_ = 1; once2_; once2_ = 0)
+// Tile loop of the calling work-group over its instance (tiles t = g, g + G, ...; tile_coords).
+#define FOR_TILES(op, wi)                                                              \
+  for (int tile_ = (wi).g; tile_ < (op).nang * (op).n_itiles; tile_ += (wi).G)         \
+    for (int j_ = 0, it_ = 0, once_ = (tile_coords((op).nang, (op).n_itiles, tile_, j_, it_), 1); once_; once_ = 0) \
+      for (int i0_ = it_ * kTileR, once2_ = 1; once2_; once2_ = 0)
 
-// Element owned by the calling thread in tile (j, i0); -1 when past nr.
+// Element owned by the calling thread in tile (j, i0); -1 for halo threads and points past nr.
 template <typename T> __device__ inline long tile_elem(const DevOp<T>& op, int j, int i0) {
-  const int s = threadIdx.x / kTileR, i = i0 + (threadIdx.x - s * kTileR);
-  return i < op.nr ? (long)j * 2 * op.nr + (long)s * op.nr + i : -1;
+  return tile_elem(op.nr, j, i0 / kTileR);
 }
 
 // Chain loop: channel j of the instance handled by work-group (j % G).
@@ -187,7 +191,7 @@ __device__ inline c2_t<T> load_c(const c2_t<T>* p, long e) { return p[e]; }
 // y = S x + ah * H x for own tiles of instance b (A of the step), with optional fused outputs.
 // The caller supplies a functor on (element, S x, H x).
 // GB: neighbour loads of a gather issued together (more registers, fewer round trips).
-template <typename T, int GB = 4, int TR = 2, typename F>
+template <typename T, int GB = kGatherBatch, int TR = 2, typename F>
 __device__ inline void apply_own(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
   const DevOp<T>& op = op_of<T>(a);
   FOR_TILES(op, wi) {
@@ -198,7 +202,7 @@ __device__ inline void apply_own(const SolveArgs& a, const WgInfo& wi, const c2_
 }
 
 // Same with the next step's fields as well: f(e, S x, H x, H_next x).
-template <typename T, int GB = 4, int TR = 2, typename F>
+template <typename T, int GB = kGatherBatch, int TR = 2, typename F>
 __device__ inline void apply_own2(const SolveArgs& a, const WgInfo& wi, const c2_t<T>* xin, Shared& sh, F&& f) {
   const DevOp<T>& op = op_of<T>(a);
   FOR_TILES(op, wi) {
@@ -264,7 +268,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
   const double2 ah = make_double2(0.0, 0.5 * a.dt);
   const c2_t<T> ahc = to_c<T>(ah);
   constexpr bool prec = PREC;
-  constexpr int kGB = 4;
+  constexpr int kGB = kGatherBatch;
   constexpr int kTR = PREC ? 4 : 2;  // the preconditioned variant has 512 registers per lane
   // the iterate and the other iterate buffer (xalt_buf: x + alpha p^ is formed there with s when the
   // half step may end the solve, and the two buffers swap roles when it does)
@@ -296,7 +300,7 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
     if (need_init != nullptr && !st.next_ready && wi.g == 0 && threadIdx.x == 0)
       __hip_atomic_fetch_add(need_init, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (so != nullptr && wi.g == 0 && threadIdx.x == 0) {
-      so->status = state == ST_DONE ? 0 : (state == ST_BREAKDOWN ? 2 : 1);
+      so->status = status_of(state);
       so->iters = st.iters;
       so->matvecs = st.matvecs;
       so->restarts = st.restarts;
@@ -402,14 +406,21 @@ __device__ inline void krylov(const SolveArgs& a, const WgInfo& wi, const KVec<T
       }
       st.rel_res = st.bb > 0 ? sqrt(rr / st.bb) : 0.0;
       if (pend) { st.state = ST_ACTIVE; st.fresh = 1; }
-      if (rr <= st.target2) {
+      const double rn = sqrt(rho.x * rho.x + rho.y * rho.y);
+      if (!isfinite(rr) || !isfinite(st.bb) || !isfinite(rn)) {
+        // a NaN or Inf in the right-hand side, the guess or the iteration: stop at once (the
+        // reductions are deterministic, so every work-group of the instance takes this branch)
+        st.true_rel_res = st.rel_res;
+        finish(ST_NONFINITE);
+      } else if (rr <= st.target2) {
         converged();
       } else if (st.iters >= max_iter) {
         finish(ST_FAILED);
       } else {
-        const double rn = sqrt(rho.x * rho.x + rho.y * rho.y);
         const double om = sqrt(st.omega.x * st.omega.x + st.omega.y * st.omega.y);
-        if (!st.fresh && (rn <= 1e-300 * (1.0 + rr) || om == 0.0)) {
+        // rho = <r^, r> vanishing (also at the start of a cycle, where r^ may be a given shadow
+        // residual) or omega vanishing: restart with r^ = r
+        if (rn <= 1e-300 * (1.0 + rr) || (!st.fresh && om == 0.0)) {
           // breakdown: restart from the same r with r^ = r; rho of the restart is ||r||^2
           st.restarts++;
           if (st.restarts > 20) {
@@ -661,7 +672,7 @@ void persistent_kernel(SolveArgs a) {
     // step runs in this launch for this instance
     const bool next_live = wi.live && k + 1 < a.n_chunk && (a.n_steps == nullptr || step + 1 < a.n_steps[wi.b]);
     const bool fuse = !MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN && inst && next_live;
-    if (!MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN) fields_to_lds(a, treg, fuse, t_mid + a.dt, sh.tl2);
+    if (!MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN) fields_to_lds(a, treg, fuse, a.t0 + (double)(step + 1) * a.dt + 0.5 * a.dt, sh.tl2);
     if (!inst) ready = false;
     // right-hand side buffers alternate between steps so the next one can be formed early
     double2* bbuf = (!MIXED && (k & 1)) ? a.bvec2 : a.bvec;
@@ -687,7 +698,7 @@ void persistent_kernel(SolveArgs a) {
         const double2* psi = a.psi + base;
         const int gs = a.guess;
         const bool direct_r = !MIXED && gs != GUESS_GIVEN;
-        apply_own<double, 4, PREC ? 4 : 2>(a, wk, psi, sh, [&](long e, double2 sx, double2 hx) {
+        apply_own<double, kGatherBatch, PREC ? 4 : 2>(a, wk, psi, sh, [&](long e, double2 sx, double2 hx) {
           const double2 bval = cfma<double>(mahc, hx, sx);
           bv[e] = bval;
           dot_acc(bb, bval, bval);
@@ -722,16 +733,22 @@ void persistent_kernel(SolveArgs a) {
       // r = b - A x0 in FP64 (the outer residual in mixed precision)
       if (!grid_barrier(gb)) { fail_steps(a, wi, k); return; }
       if (inst) {
-        double2 rr = {0, 0};
+        double2 rr = {0, 0}, rho = {0, 0};
         double2* rt = MIXED ? a.r64 + base : V.r + base;
-        apply_own<double, 4, PREC ? 4 : 2>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
+        const double2* shadow = !MIXED && a.shadow != nullptr ? a.shadow + base : nullptr;
+        apply_own<double, kGatherBatch, PREC ? 4 : 2>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
           const double2 rv = csub<double>(bv[e], cfma<double>(ahc, hx, sx));
           rt[e] = rv;
-          if (!MIXED) V.rh[base + e] = rv;
+          if (!MIXED) {
+            // shadow residual of the first cycle: r^ = r, or the caller's vector (test hook)
+            const double2 rhv = shadow != nullptr ? shadow[e] : rv;
+            V.rh[base + e] = rhv;
+            dot_acc(rho, rhv, rv);
+          }
           dot_acc(rr, rv, rv);
         });
         if (!MIXED) {
-          put_partial(a, wk, SLOT_RHO, rr, sh);
+          put_partial(a, wk, SLOT_RHO, rho, sh);
           put_partial(a, wk, SLOT_RR, rr, sh);
         } else {
           put_partial(a, wk, SLOT_ORR, rr, sh);
@@ -830,7 +847,7 @@ void persistent_kernel(SolveArgs a) {
         if (wq.live) {
           double2 rr = {0, 0};
           double2* rt = a.r64 + base;
-          apply_own<double, 4, PREC ? 4 : 2>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
+          apply_own<double, kGatherBatch, PREC ? 4 : 2>(a, wk, x, sh, [&](long e, double2 sx, double2 hx) {
             const double2 rv = csub<double>(bv[e], cfma<double>(ahc, hx, sx));
             rt[e] = rv;
             dot_acc(rr, rv, rv);
@@ -852,7 +869,7 @@ void persistent_kernel(SolveArgs a) {
         elem_own<double>(a, wk, [&](long e) { dst[e] = x[e]; });
         if (a.stats != nullptr && wk.g == 0 && threadIdx.x == 0) {
           StatsDev& o = a.stats[(size_t)k * a.B + wk.b];
-          o.status = st.state == ST_DONE ? 0 : (st.state == ST_BREAKDOWN ? 2 : 1);
+          o.status = status_of(st.state);
           o.iters = st.iters;
           o.matvecs = st.matvecs;
           o.restarts = 0;

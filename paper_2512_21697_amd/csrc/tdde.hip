@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <cstddef>
 #include <map>
 #include <string>
 #include <vector>
@@ -69,15 +70,23 @@ struct tdde_ctx {
   int ncu = 0;
   unsigned long long* marks = nullptr;
   int n_marks = 0;
+  const double2* shadow = nullptr;  // test hook: shadow residual of the first BiCGSTAB cycle of a solve
 };
 
-// persistent kernel variants: index = 2 * mixed + preconditioned
+// persistent kernel variants, index = 2 * mixed + preconditioned (each compiled in its own object
+// from persistent.hip)
+namespace tdde {
+const void* persistent_variant_0();
+const void* persistent_variant_1();
+const void* persistent_variant_2();
+const void* persistent_variant_3();
+}  // namespace tdde
 static const void* persistent_variant(int idx) {
   switch (idx) {
-    case 0: return reinterpret_cast<const void*>(persistent_kernel<false, false>);
-    case 1: return reinterpret_cast<const void*>(persistent_kernel<true, false>);
-    case 2: return reinterpret_cast<const void*>(persistent_kernel<false, true>);
-    default: return reinterpret_cast<const void*>(persistent_kernel<true, true>);
+    case 0: return persistent_variant_0();
+    case 1: return persistent_variant_1();
+    case 2: return persistent_variant_2();
+    default: return persistent_variant_3();
   }
 }
 
@@ -132,22 +141,26 @@ __global__ void zero_words(unsigned* p, int n) {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void apply_kernel(DevOp<T> op, const c2_t<T>* x, c2_t<T>* y, double2 as,
-                                                         double2 ah, const double* fvals, int n_fields, int E) {
+                                                         double2 ah, const double* fvals, int n_fields, int E, int B) {
   __shared__ TileLds<T> L;
   __shared__ TermLds tl;
-  // radial tile fastest, then instance, then channel: work-group w runs on XCD w % 8 = tile % 8
-  // (n_itiles a multiple of 8), so every instance and channel of a radial tile shares one L2 and
-  // the instances of one tile run close together (operator bands reused from L2)
-  const int it = blockIdx.x, b = blockIdx.y, j = blockIdx.z;
+  // work-group w: instance b = (w / 8) % B, tile t = (w / (8 B)) * 8 + w % 8, so tile t of every
+  // instance runs on XCD t % 8 (tile_coords: all channels of a radial tile on one XCD; the
+  // instances of a tile close together, operator bands reused from that XCD's L2)
+  const int w = blockIdx.x;
+  const int b = (w >> 3) % B;
+  const int t = (w / (8 * B)) * 8 + (w & 7);
+  if (t >= op.nang * op.n_itiles) return;  // uniform over the work-group
+  int j, it;
+  tile_coords(op.nang, op.n_itiles, t, j, it);
   terms_to_lds<T>(op, tl, [&](int m) { return fvals[(size_t)b * n_fields + op.t_field[m]]; });
   const c2_t<T>* xb = x + (size_t)b * E;
-  const int i0 = it * kTileR;
-  SH<T> r = apply_tile<T>(op, xb, j, i0, tl, L);
-  const int s = threadIdx.x / kTileR, i = i0 + (threadIdx.x - s * kTileR);
-  if (i < op.nr) {
+  SH<T> r = apply_tile<T, false, kGatherBatch, 1>(op, xb, j, it * kTileR, tl, L);
+  const long e = tile_elem(op.nr, j, it);
+  if (e >= 0) {
     c2_t<T> out = cmul<T>(to_c<T>(as), r.sx);
     out = cfma<T>(to_c<T>(ah), r.hx, out);
-    y[(size_t)b * E + (size_t)j * 2 * op.nr + (size_t)s * op.nr + i] = out;
+    y[(size_t)b * E + e] = out;
   }
 }
 
@@ -191,6 +204,7 @@ const char* tdde_status_string(tdde_status s) {
     case TDDE_OK: return "ok";
     case TDDE_NOT_CONVERGED: return "not converged";
     case TDDE_BREAKDOWN: return "breakdown";
+    case TDDE_NONFINITE: return "non-finite value";
     case TDDE_ERR_ARG: return "invalid argument";
     case TDDE_ERR_HIP: return "HIP error";
     case TDDE_ERR_NOMEM: return "out of device memory";
@@ -518,6 +532,12 @@ tdde_status tdde_debug_read_marks(tdde_ctx* c, uint64_t* host, int32_t cap) {
   return TDDE_OK;
 }
 
+tdde_status tdde_debug_set_shadow(tdde_ctx* c, const void* shadow) {
+  if (!c) return fail(c, TDDE_ERR_ARG, "null context");
+  c->shadow = static_cast<const double2*>(shadow);
+  return TDDE_OK;
+}
+
 tdde_status tdde_set_launch(tdde_ctx* c, int32_t wg_per_cu) {
   if (!c) return fail(c, TDDE_ERR_ARG, "null context");
   if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
@@ -771,10 +791,12 @@ static tdde_status launch_apply(tdde_ctx* c, const DevOp<T>& op, tdde_c128 as, t
   if (!c || !x || !y) return fail(c, TDDE_ERR_ARG, "null argument");
   if (!c->assembled || !c->field_set) return fail(c, TDDE_ERR_STATE, "assemble and set_field first");
   if (x == y) return fail(c, TDDE_ERR_ARG, "x and y must differ");
-  dim3 grid(op.n_itiles, c->d.batch, c->d.nang);
-  hipLaunchKernelGGL(apply_kernel<T>, grid, dim3(kThreads), 0, c->stream, op, (const c2_t<T>*)x, (c2_t<T>*)y,
-                     make_double2(as.re, as.im), make_double2(ah.re, ah.im), (const double*)c->fvals, c->d.n_fields,
-                     c->E);
+  const long n_tiles = (long)op.nang * op.n_itiles;
+  const long n_wg = (n_tiles + 7) / 8 * 8 * c->d.batch;  // tile_coords order, every instance (apply_kernel)
+  if (n_wg > INT32_MAX) return fail(c, TDDE_ERR_ARG, "too many tiles for one launch");
+  hipLaunchKernelGGL(apply_kernel<T>, dim3((unsigned)n_wg), dim3(kThreads), 0, c->stream, op, (const c2_t<T>*)x,
+                     (c2_t<T>*)y, make_double2(as.re, as.im), make_double2(ah.re, ah.im), (const double*)c->fvals,
+                     c->d.n_fields, c->E, c->d.batch);
   HIP_TRY(c, hipGetLastError());
   return TDDE_OK;
 }
@@ -819,9 +841,10 @@ static tdde_status run_persistent(tdde_ctx* c, SolveArgs& a, int n_chunk) {
   a.G = G;
   a.marks = c->marks;
   a.n_marks = c->n_marks;
-  hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->counters),
-                     c->n_counters);
-  hipLaunchKernelGGL(zero_words, dim3(8), dim3(256), 0, c->stream, c->bar, kBarWords);
+  // barrier words and per-step counters start at zero (a fill kernel, so the call can be captured)
+  hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(a.counters),
+                     n_chunk * kCounterPerStep);
+  hipLaunchKernelGGL(zero_words, dim3(8), dim3(256), 0, c->stream, a.bar, kBarWords);
   if (c->marks)
     hipLaunchKernelGGL(zero_words, dim3(16), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->marks),
                        2 * c->n_marks);
@@ -861,40 +884,48 @@ static SolveArgs base_args(tdde_ctx* c, const tdde_solve_opts* o) {
   a.bar = c->bar;
   a.counters = c->counters;
   a.stats = c->stats_dev;
+  a.shadow = c->shadow;
   a.n_chunk = 1;
   return a;
 }
 
-static tdde_status collect_stats(tdde_ctx* c, tdde_solve_stats* out) {
-  std::vector<StatsDev> h(c->d.batch);
-  HIP_TRY(c, hipMemcpyAsync(h.data(), c->stats_dev, h.size() * sizeof(StatsDev), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+static_assert(sizeof(StatsDev) == sizeof(tdde_solve_stats) && offsetof(StatsDev, rel_res) ==
+                  offsetof(tdde_solve_stats, rel_res) && offsetof(StatsDev, true_rel_res) ==
+                  offsetof(tdde_solve_stats, true_rel_res),
+              "device statistics must match the ABI struct");
+
+// Copy the statistics of a single-step launch to the host (synchronises the stream); bar: the
+// launch's grid-barrier words (time-out flag).
+static tdde_status collect_stats(tdde_ctx* c, tdde_solve_stats* out, const StatsDev* stats_dev, const unsigned* bar) {
+  HIP_TRY(c, hipMemcpyAsync(out, stats_dev, (size_t)c->d.batch * sizeof(StatsDev), hipMemcpyDeviceToHost, c->stream));
   unsigned err_word = 0;
-  HIP_TRY(c, hipMemcpy(&err_word, c->bar + kBarErr, sizeof(err_word), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpyAsync(&err_word, bar + kBarErr, sizeof(err_word), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (err_word != 0) return fail(c, TDDE_ERR_HIP, "grid barrier timed out (work-groups not co-resident)");
   tdde_status worst = TDDE_OK;
   for (int b = 0; b < c->d.batch; ++b) {
-    tdde_solve_stats& s = out[b];
-    s.status = h[b].status;
-    s.iters = h[b].iters;
-    s.matvecs = h[b].matvecs;
-    s.restarts = h[b].restarts;
-    s.outer_iters = h[b].outer_iters;
-    s.precs = h[b].precs;
-    s.rel_res = h[b].rel_res;
-    s.true_rel_res = h[b].true_rel_res;
-    if (h[b].status == 2) worst = TDDE_BREAKDOWN;
-    else if (h[b].status != 0 && worst == TDDE_OK) worst = TDDE_NOT_CONVERGED;
+    if (out[b].status == TDDE_NONFINITE) worst = TDDE_NONFINITE;
+    else if (out[b].status == TDDE_BREAKDOWN && worst != TDDE_NONFINITE) worst = TDDE_BREAKDOWN;
+    else if (out[b].status != 0 && worst == TDDE_OK) worst = TDDE_NOT_CONVERGED;
   }
   return worst;
 }
+static tdde_status collect_stats(tdde_ctx* c, tdde_solve_stats* out) {
+  return collect_stats(c, out, c->stats_dev, c->bar);
+}
 
-tdde_status tdde_solve(tdde_ctx* c, const void* b, void* x, const tdde_solve_opts* o, tdde_solve_stats* stats) {
+static tdde_status check_solve(tdde_ctx* c, const void* b, const void* x, const tdde_solve_opts* o) {
   if (!c || !b || !x) return fail(c, TDDE_ERR_ARG, "null argument");
   if (!c->assembled || !c->dt_set || !c->field_set) return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_field first");
   tdde_status s = check_opts(c, o);
   if (s != TDDE_OK) return s;
   if (o->guess == TDDE_GUESS_PREV) return fail(c, TDDE_ERR_ARG, "solve takes a ZERO or GIVEN guess");
+  return TDDE_OK;
+}
+
+tdde_status tdde_solve(tdde_ctx* c, const void* b, void* x, const tdde_solve_opts* o, tdde_solve_stats* stats) {
+  tdde_status s = check_solve(c, b, x, o);
+  if (s != TDDE_OK) return s;
   SolveArgs a = base_args(c, o);
   a.mode = MODE_SOLVE;
   a.b_in = (const double2*)b;

@@ -80,7 +80,7 @@ def test_beyond_dipole_full_size_apply_sampled_rows(gpu):
     special = []
     for j in (0, 1, op.nang // 2, op.nang - 1):
         for sc in (0, 1):
-            for i in (0, 1, 127, 128, nr - 33, nr - 1):  # tile edges and the ragged last tile
+            for i in (0, 1, 5, 6, 115, 116, 117, 127, 128, 231, 232, nr - 33, nr - 1):  # tile edges, ragged last tile
                 special.append(j * 2 * nr + sc * nr + i)
     rows = np.unique(np.concatenate([rng.integers(0, E, 2000), special]))
     print(f"apply done; oracle on {len(rows)} rows", flush=True)
