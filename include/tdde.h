@@ -28,8 +28,8 @@
  *     context stays usable and tdde_last_error() describes the failure.
  *   - Memory: tdde_assemble allocates every device buffer the context needs (operator copy,
  *     Krylov workspace, reduction scratch); tdde_set_dt the preconditioner factors on its first
- *     call. tdde_set_pulses, tdde_set_field, tdde_apply, tdde_solve, tdde_step,
- *     tdde_run_batched allocate nothing.
+ *     call. tdde_set_pulses, tdde_set_field, tdde_apply, tdde_solve, tdde_solve_static,
+ *     tdde_step, tdde_run_batched allocate nothing.
  */
 #ifndef TDDE_H
 #define TDDE_H
@@ -125,7 +125,8 @@ typedef struct {
 } tdde_solve_stats;
 
 /* Create a context for the given sizes on `hip_stream` (hipStream_t or NULL). Allocates nothing
- * on the device. Errors: TDDE_ERR_ARG for nonpositive sizes, half_band != 6 or n_fields > 16.
+ * on the device (it resolves, once per device, the address of the static scratch array behind
+ * tdde_solve_static). Errors: TDDE_ERR_ARG for nonpositive sizes, half_band != 6 or n_fields > 16.
  * Paper: the per-rank set-up before the time loop (Sec. 3.1, the implementation steps). */
 tdde_status tdde_create(const tdde_dims* dims, void* hip_stream, tdde_ctx** out);
 
@@ -148,8 +149,8 @@ tdde_status tdde_set_dt(tdde_ctx* ctx, double dt);
  * eq. bdpA, evaluated at the midpoint t + dt/2 of Sec. 2.4. */
 tdde_status tdde_set_pulses(tdde_ctx* ctx, const tdde_pulse* pulses);
 
-/* Explicit field values f[batch][n_fields] (host) used by tdde_apply and tdde_solve.
- * Paper: the scalar time functions f_alpha(t) that multiply the coupling terms
+/* Explicit field values f[batch][n_fields] (host) used by tdde_apply, tdde_solve and
+ * tdde_solve_static. Paper: the scalar time functions f_alpha(t) that multiply the coupling terms
  * of eq. fullH (computing H(t) for a step, Sec. 3.1 step 2a). */
 tdde_status tdde_set_field(tdde_ctx* ctx, const double* f);
 
@@ -174,6 +175,22 @@ tdde_status tdde_precond_apply(tdde_ctx* ctx, const void* v_dev, void* z_dev);
 tdde_status tdde_solve(tdde_ctx* ctx, const void* b_dev, void* x_dev, const tdde_solve_opts* opts,
                        tdde_solve_stats* stats);
 
+/* Size of the static device array behind tdde_solve_static (per GPU, held until the process ends). */
+#define TDDE_STATIC_SCRATCH_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): tdde_solve with the solve's scratch (the iterate and
+ * eight Krylov vectors, a right-hand-side copy, reduction partials, grid-barrier words, counters
+ * and the statistics) in a library-owned static device array of TDDE_STATIC_SCRATCH_BYTES per GPU
+ * instead of the context's workspace; same kernels and results as tdde_solve. Calls no allocation
+ * routine. Needs 10 * batch * nang * 2 * nr * 16 bytes plus about 240 KB; larger solves and mixed
+ * precision return TDDE_ERR_ARG before any launch (the limit is about 417,000 complex unknowns
+ * over all instances). Every call on one GPU uses the same array and finds the previous call's
+ * contents there (the kernels clear what must start at zero): calls that overlap in time on one
+ * GPU (several streams or host threads) race and give wrong results; serialise them. The context
+ * must have been created with the device current. Arguments and errors as tdde_solve. */
+tdde_status tdde_solve_static(tdde_ctx* ctx, const void* b_dev, void* x_dev, const tdde_solve_opts* opts,
+                              tdde_solve_stats* stats);
 
 /* One time step of every instance from time t: evaluates f_m(t + dt/2) from the pulses (or takes
  * row 0 of the field table), forms b = (S - i dt/2 H) psi, solves with BiCGSTAB from the chosen
@@ -217,7 +234,7 @@ tdde_status tdde_debug_phase_marks(tdde_ctx* ctx, int32_t cap);
 tdde_status tdde_debug_read_marks(tdde_ctx* ctx, uint64_t* host, int32_t cap);
 
 /* Test hook (no passage of the paper: it drives the breakdown branch of the iteration): shadow
- * residual r^ of the first BiCGSTAB cycle of every later tdde_solve, a device
+ * residual r^ of the first BiCGSTAB cycle of every later tdde_solve / tdde_solve_static, a device
  * complex128 array [batch][nang][2][nr] that must stay valid while those calls run (NULL restores
  * r^ = r0). A shadow with <r^, r0> = 0 makes rho vanish at once, and the solve restarts with
  * r^ = r; steps (tdde_step, tdde_run_batched) always take r^ = r0. */

@@ -58,7 +58,7 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"),
                         ("outer_iters", "<i4"), ("precs", "<i4"), ("rel_res", "<f8"), ("true_rel_res", "<f8")])
 
 EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field", "tdde_apply",
-           "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_step", "tdde_run_batched", "tdde_destroy",
+           "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_solve_static", "tdde_step", "tdde_run_batched", "tdde_destroy",
            "tdde_launch_info", "tdde_set_launch", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
            "tdde_debug_read_marks", "tdde_debug_set_shadow", "tdde_mlp_create", "tdde_mlp_destroy",
            "tdde_mlp_param_count", "tdde_mlp_set_params", "tdde_mlp_get_params", "tdde_mlp_get_grads",
@@ -87,6 +87,7 @@ def load():
         "tdde_apply_c64": [P, C128, C128, P, P],
         "tdde_precond_apply": [P, P, P],
         "tdde_solve": [P, P, P, C.POINTER(SolveOpts), P],
+        "tdde_solve_static": [P, P, P, C.POINTER(SolveOpts), P],
         "tdde_step": [P, P, C.c_double, P, C.POINTER(SolveOpts), P],
         "tdde_run_batched": [P, P, C.c_double, C.c_int32, C.c_int32, P, P, C.POINTER(SolveOpts), P],
         "tdde_destroy": [P],
@@ -277,10 +278,12 @@ class Solver:
         n = self.batch * self.E
         self._check(self.lib.tdde_precond_apply(self.h, _buf(v, n), _buf(z, n)))
 
-    def solve(self, b, x, opts, stats=True):
+    def solve(self, b, x, opts, stats=True, static=False):
+        """tdde_solve, or tdde_solve_static (scratch in the library's static device array) when
+        static is true."""
         out = (SolveStats * self.batch)() if stats else None
         n = self.batch * self.E
-        fn = self.lib.tdde_solve
+        fn = self.lib.tdde_solve_static if static else self.lib.tdde_solve
         st = self._check(fn(self.h, _buf(b, n), _buf(x, n), C.byref(opts), C.cast(out, C.c_void_p) if stats else None),
                          allow=(TDDE_OK, TDDE_NOT_CONVERGED, TDDE_BREAKDOWN, TDDE_NONFINITE))
         return st, ([s.as_dict() for s in out] if stats else None)

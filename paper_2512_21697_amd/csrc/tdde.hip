@@ -11,6 +11,7 @@
 #include <cstring>
 #include <cstddef>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -91,6 +92,32 @@ static const void* persistent_variant(int idx) {
 }
 
 static std::string g_create_err;
+
+// ------------------------------------------------------------------------------------------ static scratch
+// Device array behind tdde_solve_static (the entry point for callers that cannot allocate): the
+// solve's scratch lives here instead of in the context's workspace. Every GPU holds its own copy
+// from module load until the process ends. In host code `scratch` is only a host-side stand-in;
+// its device address comes from hipGetSymbolAddress, resolved once per device in tdde_create
+// (with that device current) and kept in g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[TDDE_STATIC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices] = {};
+static hipError_t g_scratch_err[kMaxDevices] = {};
+static bool g_scratch_done[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Resolve the current device's copy of `scratch` (first call on a device only).
+static void resolve_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_done[dev]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_err[dev] = e;
+  g_scratch_dev[dev] = e == hipSuccess ? ptr : nullptr;
+  g_scratch_done[dev] = true;
+}
 
 #define HIP_TRY(ctx, call)                                                                    \
   do {                                                                                        \
@@ -224,6 +251,7 @@ tdde_status tdde_create(const tdde_dims* dims, void* hip_stream, tdde_ctx** out)
     return TDDE_ERR_ARG;
   }
   if ((double)dims->nr * dims->nang * 2 > 2.0e9) { g_create_err = "instance too large"; return TDDE_ERR_ARG; }
+  resolve_scratch();
   tdde_ctx* c = new tdde_ctx();
   c->d = *dims;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -933,6 +961,77 @@ tdde_status tdde_solve(tdde_ctx* c, const void* b, void* x, const tdde_solve_opt
   if ((s = run_persistent(c, a, 1)) != TDDE_OK) return s;
   if (!stats) return TDDE_OK;
   return collect_stats(c, stats);
+}
+
+// Layout of the static scratch for one solve: 10 vectors of batch * E complex128 (iterate, r, r^, p,
+// p^, v, s, s^, t, right-hand side), the reduction partials, the grid-barrier words, one step's
+// counters and the statistics; every piece starts on a 256-byte boundary.
+struct StaticLayout {
+  size_t vec, part, bar, counters, stats, total;
+};
+static StaticLayout static_layout(const tdde_ctx* c) {
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  StaticLayout L{};
+  const size_t n = (size_t)c->d.batch * c->E;
+  L.vec = up(n * sizeof(double2));
+  size_t off = 10 * L.vec;
+  L.part = off;
+  off += up((size_t)c->ncu * kMaxWgPerCu * kSlots * sizeof(double2));
+  L.bar = off;
+  off += up(kBarWords * sizeof(unsigned));
+  L.counters = off;
+  off += up(kCounterPerStep * sizeof(int));
+  L.stats = off;
+  off += up((size_t)c->d.batch * sizeof(StatsDev));
+  L.total = off;
+  return L;
+}
+
+tdde_status tdde_solve_static(tdde_ctx* c, const void* b, void* x, const tdde_solve_opts* o,
+                              tdde_solve_stats* stats) {
+  tdde_status s = check_solve(c, b, x, o);
+  if (s != TDDE_OK) return s;
+  if (o->precision != TDDE_PREC_FP64) return fail(c, TDDE_ERR_ARG, "tdde_solve_static runs the FP64 solver only");
+  const StaticLayout L = static_layout(c);
+  if (L.total > (size_t)TDDE_STATIC_SCRATCH_BYTES)
+    return fail(c, TDDE_ERR_ARG, "tdde_solve_static: the solve needs " + std::to_string(L.total) +
+                                     " bytes of scratch, more than the static array's " +
+                                     std::to_string((long long)TDDE_STATIC_SCRATCH_BYTES) +
+                                     " (batch * nang * 2 * nr too large)");
+  int dev = 0;
+  HIP_TRY(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, TDDE_ERR_HIP, "device index out of range");
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev])
+      return fail(c, TDDE_ERR_STATE, "static scratch not resolved on this device (create the context with it current)");
+    if (g_scratch_err[dev] != hipSuccess)
+      return fail(c, TDDE_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(g_scratch_err[dev]));
+    base = static_cast<unsigned char*>(g_scratch_dev[dev]);
+  }
+  SolveArgs a = base_args(c, o);
+  double2* vec[10];
+  for (int k = 0; k < 10; ++k) vec[k] = reinterpret_cast<double2*>(base + k * L.vec);
+  KVec<double> V{vec[0], vec[1], vec[2], vec[3], vec[4], vec[5], vec[6], vec[7], vec[8]};
+  if (!a.use_prec) { V.ph = V.p; V.sh = V.s; }
+  a.v64 = V;
+  a.v32 = KVec<float>{};
+  a.bvec = vec[9];
+  a.bvec2 = nullptr;  // single solve: no next step's right-hand side
+  a.xalt = nullptr;   // single solve: no second iterate buffer
+  a.r64 = nullptr;
+  a.rhs32 = nullptr;
+  a.part = reinterpret_cast<double2*>(base + L.part);
+  a.bar = reinterpret_cast<unsigned*>(base + L.bar);
+  a.counters = reinterpret_cast<int*>(base + L.counters);
+  a.stats = reinterpret_cast<StatsDev*>(base + L.stats);
+  a.mode = MODE_SOLVE;
+  a.b_in = (const double2*)b;
+  a.x_io = (double2*)x;
+  if ((s = run_persistent(c, a, 1)) != TDDE_OK) return s;
+  if (!stats) return TDDE_OK;
+  return collect_stats(c, stats, a.stats, a.bar);
 }
 
 tdde_status tdde_step(tdde_ctx* c, void* psi, double t, const void* guess, const tdde_solve_opts* o,
