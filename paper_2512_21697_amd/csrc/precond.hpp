@@ -35,6 +35,8 @@ template <typename T> struct DevPrec {
   int m;                   // rows per segment (segments 0..P-2 have exactly m rows, m >= w)
   int P;                   // segments
   const int* block_of;     // [nang] factor block of channel j
+  const int* chain_order;  // [n_items] channel of chain work item w (-1: none), see chain_order_of
+  int n_items;
   const c2_t<T>* LU;       // [nblk][m][kPrecStride][P]: entry k of row t of segment p
   const c2_t<T>* TL;       // [nblk][P][w][w] transposed per segment: TL[p][c][r] = T_p(r, c)
   const c2_t<T>* TU;       // [nblk][P][w][w] likewise

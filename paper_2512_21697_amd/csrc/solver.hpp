@@ -183,7 +183,11 @@ template <typename T> __device__ inline long tile_elem(const DevOp<T>& op, int j
 }
 
 // Chain loop: channel j of the instance handled by work-group (j % G).
-#define FOR_CHAINS(op, wi) for (int j_ = (wi).g; j_ < (op).nang; j_ += (wi).G)
+// Work item w of the chain order (channels grouped by factor block, each block on one XCD) is taken
+// by work-group w mod G; items without a channel (-1) pad the order to whole rounds.
+#define FOR_CHAINS(pc, wi)                                                   \
+  for (int w_ = (wi).g; w_ < (pc).n_items; w_ += (wi).G)                   \
+    for (int j_ = (pc).chain_order[w_], once_ = 1; once_ && j_ >= 0; once_ = 0)
 
 template <typename T>
 __device__ inline c2_t<T> load_c(const c2_t<T>* p, long e) { return p[e]; }
@@ -236,7 +240,7 @@ __device__ inline void chains_own(const SolveArgs& a, const WgInfo& wi, const KV
                                   double2 c2, Shared& sh) {
   const DevOp<T>& op = op_of<T>(a);
   const DevPrec<T>& pc = pc_of<T>(a);
-  FOR_CHAINS(op, wi) {
+  FOR_CHAINS(pc, wi) {
     const size_t cb = base + (size_t)j_ * 2 * op.nr;
     ChainIO<T> io;
     io.r = V.r + cb;

@@ -194,7 +194,8 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(DevOp<T> op, const c2_t
 template <typename T>
 __global__ __launch_bounds__(kThreads) void precond_kernel(DevPrec<T> pc, int nr, const c2_t<T>* in, c2_t<T>* out, int E) {
   __shared__ ChainLds<T> lds;
-  const int j = blockIdx.x, b = blockIdx.y;
+  const int j = pc.chain_order[blockIdx.x], b = blockIdx.y;
+  if (j < 0) return;  // padding item (uniform over the work-group)
   const size_t cb = (size_t)b * E + (size_t)j * 2 * nr;
   ChainIO<T> io;
   io.r = nullptr;
@@ -591,6 +592,34 @@ tdde_status tdde_launch_info(tdde_ctx* c, int32_t* n_wg, int32_t* per_inst) {
   return TDDE_OK;
 }
 
+// Chain work order: channels grouped by factor block (channels of one distinct kappa share their LU
+// factors), blocks dealt to the 8 XCDs greedily by channel count, and the list of XCD x placed at
+// positions w = 8 i + x. Work-group w mod G (G a multiple of 8) runs on XCD w % 8, so the channels
+// of a block run side by side on one XCD and read its factor rows through that XCD's L2 instead of
+// from memory once per XCD. Short lists are padded with -1.
+static std::vector<int> chain_order_of(const std::vector<int>& block_of, int nblk) {
+  constexpr int kXcd = 8;
+  std::vector<std::vector<int>> members(nblk);
+  for (int j = 0; j < (int)block_of.size(); ++j) members[block_of[j]].push_back(j);
+  std::vector<int> blocks(nblk);
+  for (int b = 0; b < nblk; ++b) blocks[b] = b;
+  std::stable_sort(blocks.begin(), blocks.end(),
+                   [&](int a, int b) { return members[a].size() > members[b].size(); });
+  std::vector<std::vector<int>> lists(kXcd);
+  for (int b : blocks) {
+    int best = 0;
+    for (int x = 1; x < kXcd; ++x)
+      if (lists[x].size() < lists[best].size()) best = x;
+    lists[best].insert(lists[best].end(), members[b].begin(), members[b].end());
+  }
+  size_t len = 0;
+  for (auto& l : lists) len = std::max(len, l.size());
+  std::vector<int> order(len * kXcd, -1);
+  for (int x = 0; x < kXcd; ++x)
+    for (size_t i = 0; i < lists[x].size(); ++i) order[i * kXcd + x] = lists[x][i];
+  return order;
+}
+
 // Banded LU of M = S + i dt/2 H0 for one block, rows q = 2 i + s, plus segment coupling matrices.
 static void factor_block(const tdde_ctx* c, int j, double dt, int m, int P, std::vector<cd>& LU, std::vector<cd>& TL,
                          std::vector<cd>& TU, std::vector<cd>& CL, std::vector<cd>& CU) {
@@ -768,6 +797,10 @@ tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
     if ((s = dev_alloc(c, (float2**)&c->pc32.CU, allCU.size())) != TDDE_OK) return s;
     if ((s = upload(c, (int**)&c->pc64.block_of, c->block_of.data(), c->block_of.size())) != TDDE_OK) return s;
     c->pc32.block_of = c->pc64.block_of;
+    const std::vector<int> order = chain_order_of(c->block_of, c->nblk);
+    if ((s = upload(c, (int**)&c->pc64.chain_order, order.data(), order.size())) != TDDE_OK) return s;
+    c->pc32.chain_order = c->pc64.chain_order;
+    c->pc64.n_items = c->pc32.n_items = (int)order.size();
     c->prec_alloc = true;
   }
   c->pc64.n = c->pc32.n = n;
@@ -840,7 +873,7 @@ tdde_status tdde_precond_apply(tdde_ctx* c, const void* v, void* z) {
   if (!c || !v || !z) return fail(c, TDDE_ERR_ARG, "null argument");
   if (!c->dt_set || !c->prec_alloc) return fail(c, TDDE_ERR_STATE, "set_dt first (half_band 6 only)");
   if (v == z) return fail(c, TDDE_ERR_ARG, "input and output must differ");
-  hipLaunchKernelGGL(precond_kernel<double>, dim3(c->d.nang, c->d.batch), dim3(kThreads), 0, c->stream, c->pc64, c->d.nr,
+  hipLaunchKernelGGL(precond_kernel<double>, dim3(c->pc64.n_items, c->d.batch), dim3(kThreads), 0, c->stream, c->pc64, c->d.nr,
                      (const double2*)v, (double2*)z, c->E);
   HIP_TRY(c, hipGetLastError());
   return TDDE_OK;
