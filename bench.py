@@ -472,6 +472,8 @@ def main():
     ap.add_argument("--sub-steps", type=int, default=200, help="steps of the hydrogen / small-case sub-lines")
     ap.add_argument("--batched-steps", type=int, default=200, help="steps per instance in the batched section")
     ap.add_argument("--wg-per-cu", default="0", help="persistent work-groups per CU (1..4, 0 = default), or auto")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="skip the headline run (profiling runs of a sub-line's kernel only; no value)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="after the run, copy MIB MiB once (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -491,16 +493,22 @@ def main():
     launch = args.wg_per_cu if args.wg_per_cu == "auto" else int(args.wg_per_cu)
     tuning = {}
     _log(f"bench: gpu steps={args.steps} warmup={args.warmup}")
-    ms_step, st, launches, wall, psi = run_gpu_steps(P, torch, w3, args.steps, args.warmup, precond=1,
-                                                     guess=P.GUESS_PREV, launch=launch, info=tuning)
-    del psi
-    head = step_summary(w3, ms_step, st, launches)
+    if args.no_headline:
+        head = {"steps_per_s": None, "ms_per_step": None, "iters_per_step": None, "matvecs_per_step": None,
+                "precond_solves_per_step": None, "all_converged": None, "max_true_rel_res": None,
+                "kernel_ms_per_launch": None, "steps_per_launch": 0, "alg_bytes_per_step": 0.0, "alg_GBps": 0.0}
+        ms_step = None
+    else:
+        ms_step, st, launches, wall, psi = run_gpu_steps(P, torch, w3, args.steps, args.warmup, precond=1,
+                                                         guess=P.GUESS_PREV, launch=launch, info=tuning)
+        del psi
+        head = step_summary(w3, ms_step, st, launches)
     _log(f"bench: headline {head}")
     key = f"wg{tuning.get('wg_per_cu')}"
     tr = measured_traffic("beyond_dipole", key)
     traffic = None
     passes = None
-    if tr is not None:
+    if tr is not None and not args.no_headline:
         per_step = (tr["fetch_kib_per_step"] * tr["fetch_scale"] + tr["write_kib_per_step"] * tr["write_scale"]) * 1024.0
         traffic = per_step * head["steps_per_launch"]
         passes = per_step / max(1.0, head["iters_per_step"]) / (w3.op.n_unknowns * 16)
@@ -566,7 +574,7 @@ def main():
         _log("bench: batched sweep, learned vs plain guesses")
         sub["batched_learned"] = batched_learned_section(P, torch, args.batched_steps, args.batched_steps, log=_log)
     res["sub"] = sub
-    if "cpu" in sections:
+    if "cpu" in sections and not args.no_headline:
         _log("bench: cpu oracle baseline (extrapolated from timed pieces)")
         res["cpu_baseline"] = cpu_baseline_extrapolated(w3, head["matvecs_per_step"], head["precond_solves_per_step"],
                                                         head["iters_per_step"])

@@ -28,7 +28,7 @@
  *     context stays usable and tdde_last_error() describes the failure.
  *   - Memory: tdde_assemble allocates every device buffer the context needs (operator copy,
  *     Krylov workspace, reduction scratch); tdde_set_dt the preconditioner factors on its first
- *     call. tdde_set_pulses, tdde_set_field, tdde_apply, tdde_solve, tdde_solve_static,
+ *     call; tdde_set_field_table its table when it grows. tdde_set_pulses, tdde_set_field, tdde_apply, tdde_solve, tdde_solve_static,
  *     tdde_step, tdde_run_batched allocate nothing.
  */
 #ifndef TDDE_H
@@ -148,6 +148,23 @@ tdde_status tdde_set_dt(tdde_ctx* ctx, double dt);
  * set with tdde_set_field_table). Paper: the sin^2-envelope time functions of eq. ndpPot and
  * eq. bdpA, evaluated at the midpoint t + dt/2 of Sec. 2.4. */
 tdde_status tdde_set_pulses(tdde_ctx* ctx, const tdde_pulse* pulses);
+
+/* Field table: host array f[batch][n_rows][n_fields]; row n holds the time functions f_m at the
+ * midpoint of step n (tdde_run_batched's step index, t = t0 + (n + 1/2) dt; tdde_step takes row 0).
+ * Replaces the pulses for the steps that follow (tdde_set_pulses switches back), so the library is
+ * not tied to one pulse family: the caller tabulates any f_alpha(t) of eq. bdpA. Allocates the
+ * device copy on its first call and when the table grows. Errors: TDDE_ERR_ARG (n_rows < 1,
+ * non-finite values), TDDE_ERR_NOMEM; tdde_run_batched returns TDDE_ERR_ARG, before any launch, when
+ * a step it would run has no row. Paper: the scalar time functions of eq. fullH computed for each
+ * step (Sec. 3.1 step 2a), here supplied by the caller. */
+tdde_status tdde_set_field_table(tdde_ctx* ctx, const double* f, int32_t n_rows);
+
+/* The pulses of tdde_set_pulses evaluated on the device at the midpoints of steps step0 .. step0+n-1
+ * (t = t0 + (k + 1/2) dt, the times the time steps use, same arithmetic) into the host array
+ * f[batch][n][n_fields]; synchronises the stream. Uses the right-hand-side workspace (do not overlap
+ * with a step on another stream); batch * n * n_fields <= 2 * batch * nang * 2 * nr. Paper: the
+ * sin^2-envelope time functions of eq. ndpPot / eq. bdpA. */
+tdde_status tdde_eval_pulses(tdde_ctx* ctx, double t0, int32_t step0, int32_t n, double* f);
 
 /* Explicit field values f[batch][n_fields] (host) used by tdde_apply, tdde_solve and
  * tdde_solve_static. Paper: the scalar time functions f_alpha(t) that multiply the coupling terms

@@ -57,7 +57,7 @@ class SolveStats(C.Structure):
 STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"), ("restarts", "<i4"),
                         ("outer_iters", "<i4"), ("precs", "<i4"), ("rel_res", "<f8"), ("true_rel_res", "<f8")])
 
-EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field", "tdde_apply",
+EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field_table", "tdde_eval_pulses", "tdde_set_field", "tdde_apply",
            "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_solve_static", "tdde_step", "tdde_run_batched", "tdde_destroy",
            "tdde_launch_info", "tdde_set_launch", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
            "tdde_debug_read_marks", "tdde_debug_set_shadow", "tdde_mlp_create", "tdde_mlp_destroy",
@@ -82,6 +82,8 @@ def load():
         "tdde_assemble": [P, C.POINTER(OperatorDescC)],
         "tdde_set_dt": [P, C.c_double],
         "tdde_set_pulses": [P, P],
+        "tdde_set_field_table": [P, P, C.c_int32],
+        "tdde_eval_pulses": [P, C.c_double, C.c_int32, C.c_int32, P],
         "tdde_set_field": [P, P],
         "tdde_apply": [P, C128, C128, P, P],
         "tdde_apply_c64": [P, C128, C128, P, P],
@@ -263,6 +265,20 @@ class Solver:
                 p = pulses[b][m]
                 arr[b * self.n_fields + m] = PulseC(p.amp, p.T, p.omega, p.phase, 1 if p.envelope else 0, 0)
         self._check(self.lib.tdde_set_pulses(self.h, C.cast(arr, C.c_void_p)))
+
+    def set_field_table(self, table):
+        """Field table [batch][n_rows][n_fields] (row n: the time functions at the midpoint of step n)."""
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        if t.ndim != 3 or t.shape[0] != self.batch or t.shape[2] != self.n_fields:
+            raise ValueError("field table must be [batch][n_rows][n_fields]")
+        self._check(self.lib.tdde_set_field_table(self.h, t.ctypes.data_as(C.c_void_p), int(t.shape[1])))
+
+    def eval_pulses(self, t0, step0, n):
+        """The pulses evaluated on the device at the midpoints of steps step0 .. step0 + n - 1:
+        array [batch][n][n_fields]."""
+        out = np.zeros((self.batch, int(n), self.n_fields), dtype=np.float64)
+        self._check(self.lib.tdde_eval_pulses(self.h, float(t0), int(step0), int(n), out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def set_field(self, f):
         f = _np(np.asarray(f).reshape(self.batch, self.n_fields), np.float64)

@@ -224,6 +224,10 @@ __device__ inline bool grid_barrier(GridBar& gb, const int* watch = nullptr, int
   return !gb.failed;
 }
 
+// Midpoint time of step `step` on the axis t = t0 + step * dt (Sec. 2.4 midpoint rule), formed with an
+// explicit multiply-add so every kernel that evaluates it gets the same bits.
+__device__ inline double mid_time(double t0, int step, double dt) { return fma((double)step, dt, t0) + 0.5 * dt; }
+
 // Time function of eq. ndpPot (dipole limit): amp * env * sin(omega t + phase) on (0, T).
 struct PulseDev { double amp, T, omega, phase; int envelope, pad; };
 __device__ inline double pulse_eval(const PulseDev& p, double t) {

@@ -73,6 +73,8 @@ struct SolveArgs {
   int step0, n_chunk, n_fields, pad0;
   const int* n_steps;     // device [B] or null
   const PulseDev* pulses; // device [B][n_fields]
+  const double* ftab;     // device [B][ftab_rows][n_fields] field table (MODE_STEP; null: the pulses)
+  int ftab_rows, pad1;
   const double* fvals;    // device [B][n_fields]
   double2* psi;           // MODE_STEP state (in/out)
   const double2* guess_in;
@@ -605,6 +607,7 @@ struct TermRegs {
   double2 coef;
   PulseDev pulse;
   double fval;
+  int fi;  // field index of the term
 };
 
 __device__ inline TermRegs term_regs(const SolveArgs& a, const WgInfo& wi) {
@@ -613,17 +616,24 @@ __device__ inline TermRegs term_regs(const SolveArgs& a, const WgInfo& wi) {
   if (m < a.op64.n_terms && wi.live) {
     tr.coef = a.op64.t_coef[m];
     const int fi = a.op64.t_field[m];
+    tr.fi = fi;
     if (a.mode == MODE_STEP) tr.pulse = a.pulses[(size_t)wi.b * a.n_fields + fi];
     else tr.fval = a.fvals[(size_t)wi.b * a.n_fields + fi];
   }
   return tr;
 }
 
-// Field values at t_mid into the term table (live: the instance takes part; else all zero).
-__device__ inline void fields_to_lds(const SolveArgs& a, const TermRegs& tr, bool live, double t_mid, TermLds& tl) {
+// Field values of step `step` (time steps: row `step` of the field table, or the pulses at its
+// midpoint; single solves: the explicit values) into the term table (live: the instance takes part;
+// else all zero).
+__device__ inline void fields_to_lds(const SolveArgs& a, const TermRegs& tr, const WgInfo& wi, bool live, int step,
+                                     TermLds& tl) {
   terms_fields(a.op64.n_terms, a.op64.n_groups, tl, [&](int) {
     if (!live) return make_double2(0.0, 0.0);
-    const double f = a.mode == MODE_STEP ? pulse_eval(tr.pulse, t_mid) : tr.fval;
+    double f = tr.fval;
+    if (a.mode == MODE_STEP)
+      f = a.ftab != nullptr ? a.ftab[((size_t)wi.b * a.ftab_rows + step) * a.n_fields + tr.fi]
+                            : pulse_eval(tr.pulse, mid_time(a.t0, step, a.dt));
     return make_double2(tr.coef.x * f, tr.coef.y * f);
   });
 }
@@ -670,13 +680,12 @@ void persistent_kernel(SolveArgs a) {
     const bool inst = wi.live && (a.mode == MODE_SOLVE || a.n_steps == nullptr || step < a.n_steps[wi.b]);
     WgInfo wk = wi;
     wk.live = inst;
-    const double t_mid = a.t0 + (double)step * a.dt + 0.5 * a.dt;
-    fields_to_lds(a, treg, inst, t_mid, sh.tl);
+    fields_to_lds(a, treg, wi, inst, step, sh.tl);
     // the residual check of this step also forms the next step's right-hand side when the next
     // step runs in this launch for this instance
     const bool next_live = wi.live && k + 1 < a.n_chunk && (a.n_steps == nullptr || step + 1 < a.n_steps[wi.b]);
     const bool fuse = !MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN && inst && next_live;
-    if (!MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN) fields_to_lds(a, treg, fuse, a.t0 + (double)(step + 1) * a.dt + 0.5 * a.dt, sh.tl2);
+    if (!MIXED && a.mode == MODE_STEP && a.guess != GUESS_GIVEN) fields_to_lds(a, treg, wi, fuse, step + 1, sh.tl2);
     if (!inst) ready = false;
     // right-hand side buffers alternate between steps so the next one can be formed early
     double2* bbuf = (!MIXED && (k & 1)) ? a.bvec2 : a.bvec;

@@ -33,6 +33,10 @@ struct tdde_ctx {
   bool dt_set = false;
   bool field_set = false;
   bool pulses_set = false;
+  bool use_table = false;   // field table (tdde_set_field_table) instead of the pulses
+  double* ftab = nullptr;
+  int ftab_rows = 0;
+  size_t ftab_cap = 0;
   double dt = 0.0;
   std::vector<void*> allocs;
   // host copy of what the preconditioner needs
@@ -834,6 +838,51 @@ tdde_status tdde_set_pulses(tdde_ctx* c, const tdde_pulse* p) {
   HIP_TRY(c, hipMemcpyAsync(c->pulses, h.data(), n * sizeof(PulseDev), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->pulses_set = true;
+  c->use_table = false;
+  return TDDE_OK;
+}
+
+tdde_status tdde_set_field_table(tdde_ctx* c, const double* f, int32_t n_rows) {
+  if (!c || !f) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  if (n_rows < 1) return fail(c, TDDE_ERR_ARG, "n_rows must be positive");
+  const size_t n = (size_t)c->d.batch * n_rows * c->d.n_fields;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(f[i])) return fail(c, TDDE_ERR_ARG, "field table values must be finite");
+  if (n > c->ftab_cap) {
+    tdde_status s = dev_alloc(c, &c->ftab, n);  // the smaller table stays allocated until destroy
+    if (s != TDDE_OK) return s;
+    c->ftab_cap = n;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->ftab, f, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->ftab_rows = n_rows;
+  c->use_table = true;
+  return TDDE_OK;
+}
+
+__global__ void eval_pulses_kernel(const PulseDev* pulses, int B, int nf, double t0, int step0, int n, double dt,
+                                   double* out) {
+  const int total = B * n * nf;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int m = i % nf, k = (i / nf) % n, b = i / (nf * n);
+    out[i] = pulse_eval(pulses[(size_t)b * nf + m], mid_time(t0, step0 + k, dt));
+  }
+}
+
+tdde_status tdde_eval_pulses(tdde_ctx* c, double t0, int32_t step0, int32_t n, double* f) {
+  if (!c || !f) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled || !c->dt_set || !c->pulses_set) return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_pulses first");
+  if (n < 1) return fail(c, TDDE_ERR_ARG, "n must be positive");
+  const size_t total = (size_t)c->d.batch * n * c->d.n_fields;
+  // the values go through the right-hand-side workspace (2 * batch * E doubles)
+  if (total > (size_t)2 * c->d.batch * c->E) return fail(c, TDDE_ERR_ARG, "too many values for the workspace");
+  double* out = reinterpret_cast<double*>(c->bvec);
+  hipLaunchKernelGGL(eval_pulses_kernel, dim3((unsigned)std::min<size_t>((total + 255) / 256, 4096)), dim3(256), 0,
+                     c->stream, c->pulses, c->d.batch, c->d.n_fields, t0, step0, n, c->dt, out);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemcpyAsync(f, out, total * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return TDDE_OK;
 }
 
@@ -940,6 +989,8 @@ static SolveArgs base_args(tdde_ctx* c, const tdde_solve_opts* o) {
   a.dt = c->dt;
   a.n_fields = c->d.n_fields;
   a.pulses = c->pulses;
+  a.ftab = c->use_table ? c->ftab : nullptr;
+  a.ftab_rows = c->ftab_rows;
   a.fvals = c->fvals;
   a.part = c->part;
   a.bar = c->bar;
@@ -1070,7 +1121,8 @@ tdde_status tdde_solve_static(tdde_ctx* c, const void* b, void* x, const tdde_so
 tdde_status tdde_step(tdde_ctx* c, void* psi, double t, const void* guess, const tdde_solve_opts* o,
                       tdde_solve_stats* stats) {
   if (!c || !psi) return fail(c, TDDE_ERR_ARG, "null argument");
-  if (!c->assembled || !c->dt_set || !c->pulses_set) return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_pulses first");
+  if (!c->assembled || !c->dt_set || !(c->pulses_set || c->use_table))
+    return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_pulses or set_field_table first");
   tdde_status s = check_opts(c, o);
   if (s != TDDE_OK) return s;
   if (o->guess == TDDE_GUESS_GIVEN && !guess) return fail(c, TDDE_ERR_ARG, "GIVEN guess needs guess_dev");
@@ -1089,12 +1141,20 @@ tdde_status tdde_step(tdde_ctx* c, void* psi, double t, const void* guess, const
 tdde_status tdde_run_batched(tdde_ctx* c, void* psi, double t0, int32_t step0, int32_t n_chunk, const int32_t* n_steps,
                              const void* guess, const tdde_solve_opts* o, void* stats_dev) {
   if (!c || !psi || !n_steps) return fail(c, TDDE_ERR_ARG, "null argument");
-  if (!c->assembled || !c->dt_set || !c->pulses_set) return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_pulses first");
+  if (!c->assembled || !c->dt_set || !(c->pulses_set || c->use_table))
+    return fail(c, TDDE_ERR_STATE, "assemble, set_dt, set_pulses or set_field_table first");
   tdde_status s = check_opts(c, o);
   if (s != TDDE_OK) return s;
   if (o->guess == TDDE_GUESS_GIVEN && (!guess || n_chunk != 1))
     return fail(c, TDDE_ERR_ARG, "a GIVEN guess needs guess_dev and n_chunk == 1");
   if (n_chunk <= 0 || n_chunk > 64 || step0 < 0) return fail(c, TDDE_ERR_ARG, "1 <= n_chunk <= 64, step0 >= 0");
+  if (c->use_table)
+    for (int b = 0; b < c->d.batch; ++b) {
+      // rows of the steps this launch runs for instance b (the last one forms no further step's data)
+      const long last = std::min<long>(n_steps[b], (long)step0 + n_chunk);
+      if (last > step0 && last > c->ftab_rows)
+        return fail(c, TDDE_ERR_ARG, "field table has no row for step " + std::to_string(last - 1));
+    }
   HIP_TRY(c, hipMemcpyAsync(c->n_steps_dev, n_steps, (size_t)c->d.batch * sizeof(int), hipMemcpyHostToDevice, c->stream));
   SolveArgs a = base_args(c, o);
   a.mode = MODE_STEP;

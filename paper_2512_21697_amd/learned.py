@@ -38,13 +38,6 @@ def init_params(seed: int, n_params: int) -> np.ndarray:
     return flat
 
 
-def _field(p, t):
-    if not (0.0 < t < p.T):
-        return 0.0
-    env = math.sin(math.pi * t / p.T) ** 2 if p.envelope else 1.0
-    return p.amp * env * math.sin(p.omega * t + p.phase)
-
-
 def collect_samples(torch, op, pulses, n_steps, psi0, dt, t0=0.0, every=20, rows_per_instance=256, seed=0,
                     guess=GUESS_PREV, chunk_log=None):
     """Propagate every instance to its own n_steps and sample training rows. Returns float64 [M][16]."""
@@ -60,6 +53,9 @@ def collect_samples(torch, op, pulses, n_steps, psi0, dt, t0=0.0, every=20, rows
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
     ns = np.asarray(n_steps, dtype=np.int32)
+    # the field at the midpoint of every step, evaluated by the library's device pulses (the values the
+    # solver and the guess kernel use): fv[b][n] = f(t_n + dt/2)
+    fv = s.eval_pulses(t0, 0, int(ns.max()))[:, :, 0]
     rows = []
     comp = torch.arange(E, device=dev)
     s_of = ((comp // op.nr) % 2).to(torch.float64)
@@ -78,9 +74,8 @@ def collect_samples(torch, op, pulses, n_steps, psi0, dt, t0=0.0, every=20, rows
                 nxt = psi[gi]
                 raw[:, 8] = nxt.real
                 raw[:, 9] = nxt.imag
-                tn = t0 + n * dt
-                raw[:, 10] = _field(pulses[b][0], tn + 0.5 * dt)
-                raw[:, 11] = _field(pulses[b][0], tn - 0.5 * dt)
+                raw[:, 10] = float(fv[b, n])
+                raw[:, 11] = float(fv[b, n - 1])
                 raw[:, 12] = s_of[idx]
                 rows.append(raw)
         # rotate the history: the oldest buffer receives psi_{n+1}
