@@ -11,6 +11,7 @@ Contents (each function cites the passage of the paper it restates):
   * ``bicgstab``   textbook unpreconditioned BiCGSTAB (van der Vorst 1992)
   * ``step``       the Crank-Nicolson step (eq. solPsi, midpoint time of Sec. 2.4)
   * ``mlp``        FP64 forward / backward / Adam of the learned initial-guess network
+  * ``spectrum``   photoelectron energy spectrum dP/dE and its error integral (eq. dPdE)
 
 Parity status: every function is pinned by the non-GPU tests (dense solves, closed
 forms, invariants, brute force on tiny inputs, finite differences). Iteration counts
