@@ -37,7 +37,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 DEFAULT_WG_PER_CU = 4  # the library's default launch shape (work-groups per CU of the persistent grid)
-SECTIONS = ("c3plain", "apply", "c2", "c2d", "c1", "mixed", "batched", "cpu")
+SECTIONS = ("c3plain", "apply", "c2", "c2d", "c1", "mixed", "batched", "spectrum", "cpu")
 
 
 def _log(msg):
@@ -373,6 +373,69 @@ def apply_section(P, torch, w, reps=20):
             "GFLOPs": fl / (ms * 1e-3) / 1e9, "frac_fp64": fl / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}
 
 
+def spectrum_section(P, torch, reps=20):
+    """Photoelectron spectrum of ionised hydrogen (eq. dPdE): propagate the ground state through a
+    4-cycle pulse (w = 1, E0 = 1) at dt = 8e-3 and 4e-3 on the GPU, then time tdde_spectrum (projection onto
+    the 848 field-free levels of 21 kappa blocks inside (0.02, 3) a.u., density, grid of 300 energies)
+    and report the spectral error between the two time resolutions (the paper's convergence metric)."""
+    from workloads import spectrum as wspec
+    out = {}
+    spectra = []
+    inp = None
+    for dt in (8e-3, 4e-3):
+        w, inp = wspec.hydrogen_case(dt=dt)
+        n = int(w.n_steps[0])
+        s = P.Solver(w.op, 1)
+        try:
+            s.set_dt(dt)
+            s.set_pulses(w.pulses)
+            psi = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
+            opts = P.solve_opts(tol=1e-12, max_iter=300, guess=P.GUESS_PREV, precond=1)
+            stats = torch.zeros(n * P.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+            ns = np.array([n], dtype=np.int32)
+            t0 = time.perf_counter()
+            k = 0
+            while k < n:
+                m = min(64, n - k)
+                s.run_batched(psi, w.t0, k, m, ns, opts, stats[k * 40:(k + m) * 40])
+                k += m
+            torch.cuda.synchronize()
+            t_prop = time.perf_counter() - t0
+            st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
+            s.spectrum_setup(inp.blk_of, inp.n_lev, inp.levels, inp.edges, inp.vecs, inp.grid)
+            dp = torch.zeros(inp.grid.size, dtype=torch.float64, device="cuda:0")
+            stream = torch.cuda.current_stream()
+            s.spectrum(psi, dp)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                s.spectrum(psi, dp)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            spectra.append(dp.clone())
+            pr = dp.cpu().numpy()
+            out[f"dt_{dt:g}"] = {"steps": n, "propagation_s": t_prop, "steps_per_s": n / t_prop,
+                                  "all_converged": bool(np.all(st["status"] == 0)),
+                                  "iters_per_step": float(st["iters"].mean()),
+                                  "ionisation_in_window": float(np.sum(0.5 * (pr[1:] + pr[:-1]) * np.diff(inp.grid))),
+                                  "spectrum_ms": ms}
+            if dt == 4e-3:
+                err = s.spectrum_error(spectra[1], spectra[0])
+                out["spectral_error_dt_vs_dt2"] = float(err[0])
+            del psi, stats
+        finally:
+            s.close()
+    nr, lev = 600, int(inp.levels.size)
+    b = lev * 2 * nr * 8 + 21 * 2 * nr * 16 + inp.grid.size * 8
+    out["spectrum"] = {"kernels": "spec_project_kernel + spec_grid_kernel", "levels": lev, "grid": int(inp.grid.size),
+                       "ms": out["dt_0.004"]["spectrum_ms"], "alg_bytes": b,
+                       "alg_GBps": b / (out["dt_0.004"]["spectrum_ms"] * 1e-3) / 1e9}
+    return out
+
+
 # ------------------------------------------------------------------------------ CPU oracle baseline
 
 def host_info():
@@ -573,6 +636,9 @@ def main():
     if "batched" in sections:
         _log("bench: batched sweep, learned vs plain guesses")
         sub["batched_learned"] = batched_learned_section(P, torch, args.batched_steps, args.batched_steps, log=_log)
+    if "spectrum" in sections:
+        _log("bench: photoelectron spectrum of ionised hydrogen")
+        sub["spectrum"] = spectrum_section(P, torch)
     res["sub"] = sub
     if "cpu" in sections and not args.no_headline:
         _log("bench: cpu oracle baseline (extrapolated from timed pieces)")

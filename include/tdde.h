@@ -228,6 +228,32 @@ tdde_status tdde_run_batched(tdde_ctx* ctx, void* psi_dev, double t0, int32_t st
                              const int32_t* n_steps, const void* guess_dev, const tdde_solve_opts* opts,
                              void* stats_dev);
 
+/* Photoelectron energy spectrum, eq. dPdE: dP/dE = sum over channels (kappa, mu) of
+ * |<psi_{kappa,mu,E}|Psi>|^2 with the field-free eigenstates of each channel's radial block (Sec. 2.3:
+ * H0 v = E S v), found by diagonalisation before the run (the paper's pre-computed input, Sec. 3.1)
+ * and passed in here: n_blk eigen-blocks (channels of one block share kappa, hence H0, S and the
+ * eigenvectors: Sec. 2.2, the blocks depend on kappa only); blk_of[nang] the block of every channel;
+ * per block n_lev[b] levels inside the energy window, ascending (levels: concatenated over blocks)
+ * and edges[b][2] the nearest levels below and above the window; vecs [total levels][2][nr] the
+ * real box-normalised eigenvectors (v^T S v = 1); grid[n_grid] ascending energies. A level stands
+ * for the energy-normalised state times sqrt(dE_n), dE_n = (E_{n+1} - E_{n-1}) / 2, so the density
+ * at E_n is |v_n^T S Psi_j|^2 / dE_n; each channel's density is interpolated linearly onto the grid
+ * (zero outside its levels) and the channels are summed. Host arrays, copied; allocates the
+ * spectrum buffers (once per context). Needs real kappa-polynomial blocks (no per-channel bands).
+ * Errors: TDDE_ERR_ARG (indices, orders, sizes), TDDE_ERR_STATE (before assembly, or a second call). */
+tdde_status tdde_spectrum_setup(tdde_ctx* ctx, int32_t n_blk, const int32_t* blk_of, const int32_t* n_lev,
+                                const double* levels, const double* edges, const double* vecs, const double* grid,
+                                int32_t n_grid);
+
+/* dP/dE on the grid for every instance: psi_dev [batch][nang][2][nr] complex128, dpde_dev
+ * [batch][n_grid] double (device). No synchronisation. Paper: eq. dPdE. */
+tdde_status tdde_spectrum(tdde_ctx* ctx, const void* psi_dev, void* dpde_dev);
+
+/* Spectral error of Sec. 4 (physical validation): err[b] = integral over the grid of
+ * |P_b(E) - Q_b(E)|^2 dE (trapezoidal rule); p_dev, q_dev [batch][n_grid] double (device), err host
+ * [batch]; synchronises the stream. */
+tdde_status tdde_spectrum_error(tdde_ctx* ctx, const void* p_dev, const void* q_dev, double* err);
+
 /* Release every device buffer of the context. Accepts NULL. */
 tdde_status tdde_destroy(tdde_ctx* ctx);
 

@@ -58,7 +58,8 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"),
                         ("outer_iters", "<i4"), ("precs", "<i4"), ("rel_res", "<f8"), ("true_rel_res", "<f8")])
 
 EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field_table", "tdde_eval_pulses", "tdde_set_field", "tdde_apply",
-           "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_solve_static", "tdde_step", "tdde_run_batched", "tdde_destroy",
+           "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_solve_static", "tdde_step", "tdde_spectrum_setup", "tdde_spectrum",
+           "tdde_spectrum_error", "tdde_run_batched", "tdde_destroy",
            "tdde_launch_info", "tdde_set_launch", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
            "tdde_debug_read_marks", "tdde_debug_set_shadow", "tdde_mlp_create", "tdde_mlp_destroy",
            "tdde_mlp_param_count", "tdde_mlp_set_params", "tdde_mlp_get_params", "tdde_mlp_get_grads",
@@ -90,6 +91,9 @@ def load():
         "tdde_precond_apply": [P, P, P],
         "tdde_solve": [P, P, P, C.POINTER(SolveOpts), P],
         "tdde_solve_static": [P, P, P, C.POINTER(SolveOpts), P],
+        "tdde_spectrum_setup": [P, C.c_int32, P, P, P, P, P, P, C.c_int32],
+        "tdde_spectrum": [P, P, P],
+        "tdde_spectrum_error": [P, P, P, P],
         "tdde_step": [P, P, C.c_double, P, C.POINTER(SolveOpts), P],
         "tdde_run_batched": [P, P, C.c_double, C.c_int32, C.c_int32, P, P, C.POINTER(SolveOpts), P],
         "tdde_destroy": [P],
@@ -326,6 +330,42 @@ class Solver:
         self._check(self.lib.tdde_run_batched(self.h, _buf(psi, self.batch * self.E), float(t0), int(step0),
                                               int(n_chunk), ns.ctypes.data_as(C.c_void_p), g, C.byref(opts),
                                               _ptr(stats_dev)))
+
+    def spectrum_setup(self, blk_of, n_lev, levels, edges, vecs, grid):
+        """Eigen-blocks of the photoelectron spectrum (see include/tdde.h: tdde_spectrum_setup)."""
+        blk = _np(blk_of, np.int32)
+        nl = _np(n_lev, np.int32)
+        lv = _np(levels, np.float64)
+        ed = _np(edges, np.float64)
+        vc = _np(vecs, np.float64)
+        gr = _np(grid, np.float64)
+        if blk.shape != (self.nang,) or ed.shape != (nl.size, 2) or lv.size != int(nl.sum()) or \
+                vc.size != lv.size * 2 * self.nr:
+            raise ValueError("spectrum inputs have inconsistent shapes")
+        self._spec_ngrid = int(gr.size)
+        self._check(self.lib.tdde_spectrum_setup(
+            self.h, int(nl.size), blk.ctypes.data_as(C.c_void_p), nl.ctypes.data_as(C.c_void_p),
+            lv.ctypes.data_as(C.c_void_p), ed.ctypes.data_as(C.c_void_p), vc.ctypes.data_as(C.c_void_p),
+            gr.ctypes.data_as(C.c_void_p), int(gr.size)))
+
+    def spectrum(self, psi, out):
+        """dP/dE of every instance into the device float64 tensor out [batch][n_grid]."""
+        n = self.batch * self.E
+        if str(out.dtype) != "torch.float64" or not out.is_cuda or not out.is_contiguous() or \
+                out.numel() != self.batch * self._spec_ngrid:
+            raise ValueError("out must be a contiguous device float64 tensor [batch][n_grid]")
+        self._check(self.lib.tdde_spectrum(self.h, _buf(psi, n), C.c_void_p(out.data_ptr())))
+
+    def spectrum_error(self, p, q):
+        """Trapezoidal integral of |p - q|^2 over the grid, per instance (host array [batch])."""
+        for t in (p, q):
+            if str(t.dtype) != "torch.float64" or not t.is_cuda or not t.is_contiguous() or \
+                    t.numel() != self.batch * self._spec_ngrid:
+                raise ValueError("spectra must be contiguous device float64 tensors [batch][n_grid]")
+        err = np.zeros(self.batch, dtype=np.float64)
+        self._check(self.lib.tdde_spectrum_error(self.h, C.c_void_p(p.data_ptr()), C.c_void_p(q.data_ptr()),
+                                                 err.ctypes.data_as(C.c_void_p)))
+        return err
 
     def set_shadow(self, shadow):
         """Test hook: shadow residual of the first BiCGSTAB cycle of later solves (None: r^ = r0).

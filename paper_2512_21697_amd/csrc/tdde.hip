@@ -76,6 +76,16 @@ struct tdde_ctx {
   unsigned long long* marks = nullptr;
   int n_marks = 0;
   const double2* shadow = nullptr;  // test hook: shadow residual of the first BiCGSTAB cycle of a solve
+  // photoelectron spectrum (tdde_spectrum_setup)
+  bool spec_set = false;
+  int spec_nblk = 0, spec_maxlev = 0, spec_ngrid = 0;
+  int* spec_blk_of = nullptr;     // [nang] eigen-block of every channel
+  int* spec_lev0 = nullptr;       // [nblk + 1] first level of every block
+  double* spec_E = nullptr;       // [total levels + 2 nblk]: per block the level below, its levels, the level above
+  double* spec_U = nullptr;       // [total levels][2][nr] S v_n
+  double* spec_grid = nullptr;    // [n_grid]
+  double* spec_dens = nullptr;    // [batch][nang][max levels]
+  double* spec_err = nullptr;     // [batch]
 };
 
 // persistent kernel variants, index = 2 * mixed + preconditioned (each compiled in its own object
@@ -1168,3 +1178,208 @@ tdde_status tdde_run_batched(tdde_ctx* c, void* psi, double t0, int32_t step0, i
   return run_persistent(c, a, n_chunk);
 }
 
+
+// ------------------------------------------------------------------------------------------ spectrum
+// Photoelectron energy spectrum of eq. dPdE: dP/dE(E_n) = sum over channels |v_n^T S psi_j|^2 / dE_n
+// with the caller's field-free eigenvectors v_n of the channel's radial block (box-normalised,
+// v^T S v = 1), dE_n = (E_{n+1} - E_{n-1}) / 2, each channel's density interpolated linearly onto the
+// energy grid (zero outside its levels) and summed in channel order.
+
+// u_n = S v_n for every level (S of the block's kappa; copy when S = I).
+__global__ void spec_sv_kernel(DevOp<double> op, const int* blk_kb, const int* lev0, int nblk, const double* v,
+                               double* u) {
+  const int nr = op.nr, nb = op.nb;
+  const long total = (long)lev0[nblk] * 2 * nr;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long n = e / (2 * nr);
+    const int q = (int)(e - n * 2 * nr), s = q / nr, i = q - s * nr;
+    if (op.n_s == 0) { u[e] = v[e]; continue; }
+    int b = 0;
+    while (b + 1 < nblk && lev0[b + 1] <= n) ++b;
+    const int kb = blk_kb[b];
+    const double* vn = v + n * 2 * nr;
+    double acc = 0.0;
+    for (int s2 = 0; s2 < 2; ++s2) {
+      if (!op.pq_s && s2 != s) continue;
+      const double* band = op.s_blk + ((size_t)kb * 4 + s * 2 + s2) * nb * nr;
+      for (int d = 0; d < nb; ++d) {
+        const int i2 = i + d - op.hb;
+        if (i2 >= 0 && i2 < nr) acc = fma(band[(size_t)d * nr + i], vn[(size_t)s2 * nr + i2], acc);
+      }
+    }
+    u[e] = acc;
+  }
+}
+
+// dens[b][j][k] = |u_{n}^T psi[b][j]|^2 / dE_n for the levels n = lev0[blk] + k of channel j's block.
+// One work-group per (channel, instance); wave w takes levels k = w, w + 4, ...
+__global__ __launch_bounds__(kThreads) void spec_project_kernel(const int* blk_of, const int* lev0, const double* Ebuf,
+                                                               const double* u, const double2* psi, int nr, int nang,
+                                                               int maxlev, double* dens) {
+  const int j = blockIdx.x, b = blockIdx.y;
+  const int blk = blk_of[j];
+  const int n0 = lev0[blk], nl = lev0[blk + 1] - n0;
+  const double* Eb = Ebuf + n0 + 2 * blk;  // Eb[0] level below, Eb[1 .. nl] levels, Eb[nl + 1] level above
+  const double2* x = psi + ((size_t)b * nang + j) * 2 * nr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int k = wave; k < nl; k += kThreads / 64) {
+    const double* un = u + (size_t)(n0 + k) * 2 * nr;
+    double re = 0.0, im = 0.0;
+    for (int q = lane; q < 2 * nr; q += 64) {
+      const double w = un[q];
+      const double2 xv = x[q];
+      re = fma(w, xv.x, re);
+      im = fma(w, xv.y, im);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off, 64);
+      im += __shfl_xor(im, off, 64);
+    }
+    if (lane == 0) {
+      const double dE = 0.5 * (Eb[k + 2] - Eb[k]);
+      dens[((size_t)b * nang + j) * maxlev + k] = (re * re + im * im) / dE;
+    }
+  }
+}
+
+// dpde[b][g]: sum over channels (in order) of the linear interpolation of the channel's density at
+// grid[g]; zero outside the channel's first and last level.
+__global__ void spec_grid_kernel(const int* blk_of, const int* lev0, const double* Ebuf, const double* dens,
+                                 const double* grid, int n_grid, int nang, int maxlev, int B, double* dpde) {
+  const int total = B * n_grid;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int b = e / n_grid, g = e - b * n_grid;
+    const double x = grid[g];
+    double acc = 0.0;
+    for (int j = 0; j < nang; ++j) {
+      const int blk = blk_of[j];
+      const int n0 = lev0[blk], nl = lev0[blk + 1] - n0;
+      if (nl == 0) continue;
+      const double* L = Ebuf + n0 + 2 * blk + 1;  // the block's levels, ascending
+      if (x < L[0] || x > L[nl - 1]) continue;
+      int lo = 0, hi = nl - 1;  // L[lo] <= x <= L[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L[mid] <= x) lo = mid; else hi = mid;
+      }
+      const double* d = dens + ((size_t)b * nang + j) * maxlev;
+      if (nl == 1) { acc += d[0]; continue; }
+      const double t = (x - L[lo]) / (L[hi] - L[lo]);
+      acc += d[lo] + t * (d[hi] - d[lo]);
+    }
+    dpde[e] = acc;
+  }
+}
+
+// err[b] = sum_g (|p - q|^2 at g and g + 1, averaged) * (grid[g + 1] - grid[g]): the trapezoidal
+// integral of the squared difference; one work-group per instance, fixed summation order.
+__global__ __launch_bounds__(kThreads) void spec_error_kernel(const double* p, const double* q, const double* grid,
+                                                             int n_grid, double* err) {
+  __shared__ double red[2 * kThreads / 64];
+  const int b = blockIdx.x;
+  const double* pb = p + (size_t)b * n_grid;
+  const double* qb = q + (size_t)b * n_grid;
+  double acc = 0.0;
+  for (int g = threadIdx.x; g + 1 < n_grid; g += kThreads) {
+    const double d0 = pb[g] - qb[g], d1 = pb[g + 1] - qb[g + 1];
+    acc += 0.5 * (d0 * d0 + d1 * d1) * (grid[g + 1] - grid[g]);
+  }
+  const double2 t = wg_sum2(make_double2(acc, 0.0), red);
+  if (threadIdx.x == 0) err[b] = t.x;
+}
+
+tdde_status tdde_spectrum_setup(tdde_ctx* c, int32_t n_blk, const int32_t* blk_of, const int32_t* n_lev,
+                                const double* levels, const double* edges, const double* vecs, const double* grid,
+                                int32_t n_grid) {
+  if (!c || !blk_of || !n_lev || !levels || !edges || !vecs || !grid) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  if (c->spec_set) return fail(c, TDDE_ERR_STATE, "spectrum already set up");
+  if (c->has_chan) return fail(c, TDDE_ERR_ARG, "spectrum needs real kappa-polynomial blocks (no per-channel bands)");
+  const int nang = c->d.nang, nr = c->d.nr;
+  if (n_blk < 1 || n_grid < 2) return fail(c, TDDE_ERR_ARG, "n_blk >= 1 and n_grid >= 2 required");
+  std::vector<int> kb_of_blk(n_blk, -1);
+  for (int j = 0; j < nang; ++j) {
+    if (blk_of[j] < 0 || blk_of[j] >= n_blk) return fail(c, TDDE_ERR_ARG, "block index out of range");
+    if (kb_of_blk[blk_of[j]] < 0) kb_of_blk[blk_of[j]] = j;
+    else if (c->kappa[kb_of_blk[blk_of[j]]] != c->kappa[j])
+      return fail(c, TDDE_ERR_ARG, "channels of one eigen-block must share kappa");
+  }
+  std::vector<int> lev0(n_blk + 1, 0);
+  int maxlev = 1;
+  for (int b = 0; b < n_blk; ++b) {
+    if (n_lev[b] < 0) return fail(c, TDDE_ERR_ARG, "negative level count");
+    lev0[b + 1] = lev0[b] + n_lev[b];
+    maxlev = std::max(maxlev, (int)n_lev[b]);
+  }
+  const int total = lev0[n_blk];
+  std::vector<double> Ebuf((size_t)total + 2 * n_blk);
+  for (int b = 0; b < n_blk; ++b) {
+    double* dst = Ebuf.data() + lev0[b] + 2 * b;
+    dst[0] = edges[2 * b];
+    for (int k = 0; k < n_lev[b]; ++k) dst[1 + k] = levels[lev0[b] + k];
+    dst[n_lev[b] + 1] = edges[2 * b + 1];
+    for (int k = 0; k <= n_lev[b]; ++k)
+      if (!(dst[k + 1] > dst[k])) return fail(c, TDDE_ERR_ARG, "levels (with the edges) must ascend strictly");
+  }
+  for (int g = 0; g + 1 < n_grid; ++g)
+    if (!(grid[g + 1] > grid[g])) return fail(c, TDDE_ERR_ARG, "grid must ascend strictly");
+  // the kappa block (distinct-kappa index of the operator) of each eigen-block
+  std::vector<int> kblk(nang);
+  {
+    std::map<double, int> seen;
+    for (int j = 0; j < nang; ++j) {
+      auto it = seen.find(c->kappa[j]);
+      if (it == seen.end()) it = seen.emplace(c->kappa[j], (int)seen.size()).first;
+      kblk[j] = it->second;
+    }
+  }
+  std::vector<int> blk_kb(n_blk, 0);
+  for (int b = 0; b < n_blk; ++b) blk_kb[b] = kb_of_blk[b] >= 0 ? kblk[kb_of_blk[b]] : 0;
+  tdde_status s;
+  double* v_dev = nullptr;
+  int* blk_kb_dev = nullptr;
+  if ((s = upload(c, &c->spec_blk_of, blk_of, nang)) != TDDE_OK) return s;
+  if ((s = upload(c, &c->spec_lev0, lev0.data(), lev0.size())) != TDDE_OK) return s;
+  if ((s = upload(c, &blk_kb_dev, blk_kb.data(), blk_kb.size())) != TDDE_OK) return s;
+  if ((s = upload(c, &c->spec_E, Ebuf.data(), Ebuf.size())) != TDDE_OK) return s;
+  if ((s = upload(c, &v_dev, vecs, (size_t)total * 2 * nr)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->spec_U, (size_t)total * 2 * nr)) != TDDE_OK) return s;
+  if ((s = upload(c, &c->spec_grid, grid, n_grid)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->spec_dens, (size_t)c->d.batch * nang * maxlev)) != TDDE_OK) return s;
+  if ((s = dev_alloc(c, &c->spec_err, (size_t)c->d.batch)) != TDDE_OK) return s;
+  if (total > 0) {
+    hipLaunchKernelGGL(spec_sv_kernel, dim3(1024), dim3(256), 0, c->stream, c->op64, blk_kb_dev, c->spec_lev0, n_blk,
+                       v_dev, c->spec_U);
+    HIP_TRY(c, hipGetLastError());
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->spec_nblk = n_blk;
+  c->spec_maxlev = maxlev;
+  c->spec_ngrid = n_grid;
+  c->spec_set = true;
+  return TDDE_OK;
+}
+
+tdde_status tdde_spectrum(tdde_ctx* c, const void* psi, void* dpde) {
+  if (!c || !psi || !dpde) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->spec_set) return fail(c, TDDE_ERR_STATE, "tdde_spectrum_setup first");
+  const int nang = c->d.nang, B = c->d.batch;
+  hipLaunchKernelGGL(spec_project_kernel, dim3(nang, B), dim3(kThreads), 0, c->stream, c->spec_blk_of, c->spec_lev0,
+                     c->spec_E, c->spec_U, (const double2*)psi, c->d.nr, nang, c->spec_maxlev, c->spec_dens);
+  const int tot = B * c->spec_ngrid;
+  hipLaunchKernelGGL(spec_grid_kernel, dim3((tot + 255) / 256), dim3(256), 0, c->stream, c->spec_blk_of, c->spec_lev0,
+                     c->spec_E, c->spec_dens, c->spec_grid, c->spec_ngrid, nang, c->spec_maxlev, B, (double*)dpde);
+  HIP_TRY(c, hipGetLastError());
+  return TDDE_OK;
+}
+
+tdde_status tdde_spectrum_error(tdde_ctx* c, const void* p, const void* q, double* err) {
+  if (!c || !p || !q || !err) return fail(c, TDDE_ERR_ARG, "null argument");
+  if (!c->spec_set) return fail(c, TDDE_ERR_STATE, "tdde_spectrum_setup first");
+  hipLaunchKernelGGL(spec_error_kernel, dim3(c->d.batch), dim3(kThreads), 0, c->stream, (const double*)p,
+                     (const double*)q, c->spec_grid, c->spec_ngrid, c->spec_err);
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipMemcpyAsync(err, c->spec_err, (size_t)c->d.batch * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TDDE_OK;
+}
