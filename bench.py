@@ -37,7 +37,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 DEFAULT_WG_PER_CU = 4  # the library's default launch shape (work-groups per CU of the persistent grid)
-SECTIONS = ("c3plain", "apply", "c2", "c2d", "c1", "mixed", "batched", "spectrum", "cpu")
+SECTIONS = ("c3plain", "apply", "c2", "c2d", "c1", "mixed", "batched", "spectrum", "beyond", "cpu")
 
 
 def _log(msg):
@@ -636,6 +636,16 @@ def main():
     if "batched" in sections:
         _log("bench: batched sweep, learned vs plain guesses")
         sub["batched_learned"] = batched_learned_section(P, torch, args.batched_steps, args.batched_steps, log=_log)
+    if "beyond" in sections:
+        _log("bench: physical beyond-dipole hydrogen operator")
+        from workloads import beyond
+        wb = beyond.workload(nr=600, kappa_max=6, mu2_max=5, l_max=3)
+        sb = step_section(P, torch, wb, args.sub_steps, 5, 1,
+                          label="hydrogen in the beyond-dipole pulse (eq. bdpA): nr=600, |kappa|<=6, |mu|<=5/2 "
+                                "(60 channels), l<=3 (96 terms), E0=1, w=1, from T/4")
+        sb["apply"] = apply_section(P, torch, wb)
+        sub["beyond_dipole_physical"] = sb
+        del wb
     if "spectrum" in sections:
         _log("bench: photoelectron spectrum of ionised hydrogen")
         sub["spectrum"] = spectrum_section(P, torch)

@@ -14,7 +14,7 @@ constexpr int kMaxHB = kHB;
 // hb points on either side the halo of the radial band.
 constexpr int kStage = kThreads / 2;
 constexpr int kTileR = kStage - 2 * kHB;
-constexpr int kMaxTerms = 32;    // largest number of coupling terms
+constexpr int kMaxTerms = 128;   // largest number of coupling terms (the beyond-dipole operator: 24 per l)
 constexpr int kMaxGroup = 8;     // coupling terms staged together (one group: union angular pattern)
 constexpr int kMaxFields = 16;   // largest number of time functions per instance
 

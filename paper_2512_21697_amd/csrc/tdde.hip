@@ -453,7 +453,7 @@ tdde_status tdde_assemble(tdde_ctx* c, const tdde_operator_desc* o) {
   if (!o->kappa) return fail(c, TDDE_ERR_ARG, "kappa is required");
   if (o->n_h < 0 || o->n_h > 4 || (o->n_h > 0 && !o->h_poly)) return fail(c, TDDE_ERR_ARG, "n_h must be 0..4 with h_poly");
   if (o->n_s < 0 || o->n_s > 3 || (o->n_s > 0 && !o->s_poly)) return fail(c, TDDE_ERR_ARG, "n_s must be 0..3 with s_poly");
-  if (o->n_terms < 0 || o->n_terms > kMaxTerms) return fail(c, TDDE_ERR_ARG, "n_terms must be 0..32");
+  if (o->n_terms < 0 || o->n_terms > kMaxTerms) return fail(c, TDDE_ERR_ARG, "n_terms must be 0..128");
   if (o->n_terms > 0 && (!o->a_rowptr || !o->a_off || !o->a_col || !o->a_val || !o->r_band || !o->kpow || !o->coef ||
                          !o->field))
     return fail(c, TDDE_ERR_ARG, "coupling arrays missing");

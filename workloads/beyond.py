@@ -36,7 +36,7 @@ import numpy as np
 import scipy.sparse as sp
 from scipy.special import spherical_jn
 
-from .desc import CouplingTerm, OperatorDesc, Pulse
+from .desc import CouplingTerm, OperatorDesc, Pulse, Workload
 from . import dkb
 
 
@@ -205,3 +205,21 @@ def hydrogen_beyond_dipole(nr: int = 300, r_max: float = 60.0, kappa_max: int = 
     op = OperatorDesc(nr=nr, nang=len(chans), hb=dkb.HB, kappa=np.array([k for k, _ in chans], dtype=np.float64),
                       h_poly=h_poly, s_poly=s_poly, terms=terms, n_fields=len(fs))
     return op, chans, basis, fs, T
+
+
+def workload(nr: int = 300, r_max: float = 60.0, kappa_max: int = 4, mu2_max: int = 3, l_max: int = 3,
+             E0: float = 1.0, omega: float = 1.0, cycles: int = 2, dt: float = 4e-3, t0_frac: float = 0.25,
+             n_steps: int = 20):
+    """One instance: the hydrogen ground state (kappa = -1, mu = 1/2) in the beyond-dipole pulse,
+    started at t0 = t0_frac * T (the coupling switched on)."""
+    op, chans, basis, fs, T = hydrogen_beyond_dipole(nr, r_max, kappa_max, mu2_max, l_max, E0, omega, cycles)
+    j0 = chans.index((-1, 1))
+    w, v = dkb.bound_states(op.h_poly, op.s_poly, -1.0, nr, op.hb, n_states=1)
+    S = dkb.sparse_block(op.s_poly, -1.0, nr, op.hb)
+    vec = v[:, 0] / math.sqrt(v[:, 0] @ (S @ v[:, 0]))
+    psi0 = np.zeros((1, op.nang, 2, nr), dtype=np.complex128)
+    psi0[0, j0, 0] = vec[:nr]
+    psi0[0, j0, 1] = vec[nr:]
+    return Workload("beyond", op, psi0, [fs], dt=dt, t0=t0_frac * T, n_steps=np.array([n_steps], dtype=np.int32),
+                    tol=1e-12, meta={"T": T, "E_ground": float(w[0]), "kappa_max": kappa_max, "mu2_max": mu2_max,
+                                     "l_max": l_max, "E0": E0, "omega": omega})
