@@ -37,6 +37,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 DEFAULT_WG_PER_CU = 4  # the library's default launch shape (work-groups per CU of the persistent grid)
+DEFAULT_SEGMENT = 24   # the library's default least rows per preconditioner segment
 SECTIONS = ("c3plain", "apply", "c2", "c2d", "c1", "mixed", "batched", "spectrum", "beyond", "cpu")
 
 
@@ -132,43 +133,59 @@ def measured_traffic(name, launch_key):
 
 # ------------------------------------------------------------------------------ GPU runs
 
-def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0, launch=0, info=None):
+def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0, launch=0, info=None,
+                  segment=None):
     """Run warmup + timed steps of one instance in persistent chunks.
 
     launch: work-groups per CU of the persistent grid (1..4, 0 = library default), or "auto" to
     let the autotuner time one chunk of steps (on a scratch copy of the state, before the warmup)
-    under every shape and keep the fastest; ``info`` (a dict) receives the choice and the timings.
+    under every shape and keep the fastest. segment: least rows per preconditioner segment (None =
+    library default), or "auto" to tune it the same way (preconditioned runs only). ``info`` (a dict)
+    receives the choices, the timings and the grid actually launched.
     Returns (ms_per_step, stats array, [(kernel ms, steps) per launch], wall seconds, final state)."""
-    from paper_2512_21697_amd.autotune import tune_launch
+    from paper_2512_21697_amd.autotune import tune_launch, tune_segment
     s = P.Solver(w.op, 1)
     try:
+        if segment not in (None, "auto"):
+            s.set_prec_segment(int(segment))
         s.set_dt(w.dt)
         s.set_pulses(w.pulses)
         opts = P.solve_opts(tol=1e-12, max_iter=300, guess=guess, precond=precond, precision=precision,
                             inner_tol=1e-5, max_outer=20)
         psi = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
         stream = torch.cuda.current_stream()
+        tune_chunk = min(chunk, 20)
+        scratch = torch.empty_like(psi)
+        tune_stats = torch.zeros(tune_chunk * 40, dtype=torch.uint8, device="cuda:0")
+        tune_n = np.array([tune_chunk], dtype=np.int32)
+
+        def one_chunk():
+            scratch.copy_(psi)
+            s.run_batched(scratch, w.t0, 0, tune_chunk, tune_n, opts, tune_stats)
+
         if launch == "auto":
-            scratch = torch.empty_like(psi)
-            tune_stats = torch.zeros(chunk * 40, dtype=torch.uint8, device="cuda:0")
-            tune_n = np.array([chunk], dtype=np.int32)
-
-            def one_chunk():
-                scratch.copy_(psi)
-                s.run_batched(scratch, w.t0, 0, chunk, tune_n, opts, tune_stats)
-
-            best, times = tune_launch(s, one_chunk, prefer=DEFAULT_WG_PER_CU)
-            del scratch, tune_stats
+            best, times, grids = tune_launch(s, one_chunk, prefer=DEFAULT_WG_PER_CU)
             if info is not None:
                 info["wg_per_cu"] = best
                 info["ms_per_chunk"] = {str(k): round(v * 1e3, 3) for k, v in times.items()}
-                info["chunk_steps"] = chunk
+                info["grid_per_shape"] = {str(k): g for k, g in grids.items()}
+                info["chunk_steps"] = tune_chunk
         else:
             s.set_launch(int(launch))
             if info is not None:
                 info["wg_per_cu"] = int(launch) or DEFAULT_WG_PER_CU
+        if segment == "auto" and precond:
+            best_m, mtimes = tune_segment(s, w.dt, one_chunk, prefer=DEFAULT_SEGMENT)
+            if info is not None:
+                info["segment_rows"] = best_m
+                info["ms_per_chunk_by_segment"] = {str(k): round(v * 1e3, 3) for k, v in mtimes.items()}
+        elif info is not None and precond:
+            info["segment_rows"] = int(segment) if segment not in (None, "auto") else DEFAULT_SEGMENT
+        one_chunk()
+        torch.cuda.synchronize()
+        del scratch, tune_stats
         if info is not None:
-            info["n_wg"], info["wg_per_instance"] = s.launch_info()
+            info["n_wg"], info["wg_per_instance"] = s.launch_info()  # the grid of the launches that follow
         total = warmup + steps
         n_steps = np.array([total], dtype=np.int32)
         stats = torch.zeros(total * 40, dtype=torch.uint8, device="cuda:0")
@@ -275,12 +292,13 @@ def tune_batched(P, torch, w5, steps=8):
             scratch.copy_(psi)
             s.run_batched(scratch, w5.t0, 0, steps, ns, opts, stats)
 
-        best, times = tune_launch(s, one_launch, prefer=DEFAULT_WG_PER_CU)
+        best, times, grids = tune_launch(s, one_launch, prefer=DEFAULT_WG_PER_CU)
         n_wg, per_inst = s.launch_info()
         del psi, scratch, stats
     finally:
         s.close()
     return {"wg_per_cu": best, "ms_per_launch": {str(k): round(v * 1e3, 3) for k, v in times.items()},
+            "grid_per_shape": {str(k): g for k, g in grids.items()},
             "launch_steps": steps, "n_wg": n_wg, "wg_per_instance": per_inst}
 
 
@@ -312,7 +330,7 @@ def batched_learned_section(P, torch, train_steps, eval_steps, n_train=200, trai
         t0 = time.perf_counter()
         losses = learned.train(torch, net, raw, n_iter=800, batch_rows=16384, lr=1e-3)
         t_train = time.perf_counter() - t0
-        ns = np.minimum(w5.n_steps, eval_steps)
+        ns = w5.n_steps.copy() if eval_steps <= 0 else np.minimum(w5.n_steps, eval_steps)
         launch = tune_batched(P, torch, w5)
         if log:
             log(f"bench: batched launch shape {launch}")
@@ -533,8 +551,12 @@ def main():
     ap.add_argument("--sections", default=",".join(SECTIONS),
                     help="comma list of sub-lines to run beside the headline: " + ",".join(SECTIONS) + " (or none)")
     ap.add_argument("--sub-steps", type=int, default=200, help="steps of the hydrogen / small-case sub-lines")
-    ap.add_argument("--batched-steps", type=int, default=200, help="steps per instance in the batched section")
-    ap.add_argument("--wg-per-cu", default="0", help="persistent work-groups per CU (1..4, 0 = default), or auto")
+    ap.add_argument("--batched-steps", type=int, default=0,
+                    help="cap on the steps per instance in the batched section (0: every instance's own length, "
+                         "400-1200 steps)")
+    ap.add_argument("--train-steps", type=int, default=200, help="steps per training trajectory of the learned guess")
+    ap.add_argument("--wg-per-cu", default="auto", help="persistent work-groups per CU (1..4, 0 = default), or auto")
+    ap.add_argument("--segment", default="auto", help="least rows per preconditioner segment, or auto")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline run (profiling runs of a sub-line's kernel only; no value)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -562,12 +584,13 @@ def main():
                 "kernel_ms_per_launch": None, "steps_per_launch": 0, "alg_bytes_per_step": 0.0, "alg_GBps": 0.0}
         ms_step = None
     else:
+        seg = args.segment if args.segment == "auto" else int(args.segment)
         ms_step, st, launches, wall, psi = run_gpu_steps(P, torch, w3, args.steps, args.warmup, precond=1,
-                                                         guess=P.GUESS_PREV, launch=launch, info=tuning)
+                                                         guess=P.GUESS_PREV, launch=launch, info=tuning, segment=seg)
         del psi
         head = step_summary(w3, ms_step, st, launches)
     _log(f"bench: headline {head}")
-    key = f"wg{tuning.get('wg_per_cu')}"
+    key = f"grid{tuning.get('n_wg')}_seg{tuning.get('segment_rows')}"
     tr = measured_traffic("beyond_dipole", key)
     traffic = None
     passes = None
@@ -635,7 +658,7 @@ def main():
                     P, torch, w1, 20, 5, 0, guess=g, label=f"N=3200 {'t0=T/4' if drv else 't0=0'}")
     if "batched" in sections:
         _log("bench: batched sweep, learned vs plain guesses")
-        sub["batched_learned"] = batched_learned_section(P, torch, args.batched_steps, args.batched_steps, log=_log)
+        sub["batched_learned"] = batched_learned_section(P, torch, args.train_steps, args.batched_steps, log=_log)
     if "beyond" in sections:
         _log("bench: physical beyond-dipole hydrogen operator")
         from workloads import beyond

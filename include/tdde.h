@@ -266,6 +266,22 @@ tdde_status tdde_destroy(tdde_ctx* ctx);
  * assembly. */
 tdde_status tdde_set_launch(tdde_ctx* ctx, int32_t wg_per_cu);
 
+/* Graph mode (on != 0) for tdde_step / tdde_run_batched / tdde_solve: the launch sequence of a
+ * persistent chunk (two fill kernels and the cooperative solver launch) is captured into a HIP graph
+ * on the context's stream once per kernel variant and grid and replayed with each call's arguments
+ * (the paper runs its time loop fully on the device, Sec. 3.3; a graph removes the per-chunk launch
+ * work from the host). The context's stream must not be the legacy default stream. A runtime that
+ * cannot capture the cooperative launch makes the call return TDDE_ERR_HIP with the HIP error text
+ * (the context stays usable in direct mode). Off by default; phase marks use direct launches. */
+tdde_status tdde_set_graph(tdde_ctx* ctx, int32_t on);
+
+/* Launch-shape knob of the preconditioner's segmented triangular solves (eq. matrixM applied
+ * through its LU factors): each channel's 2 nr rows are split into segments of at least min_rows rows
+ * (one per thread, at most 256 per channel; default 24). Longer segments mean fewer boundary
+ * matrices and longer sequential substitution chains; the autotuner times the choices. Takes effect
+ * at the next tdde_set_dt (which refactors). TDDE_ERR_ARG when min_rows < 13 or > 4096. */
+tdde_status tdde_set_prec_segment(tdde_ctx* ctx, int32_t min_rows);
+
 /* Persistent-grid size actually used (work-groups) and the per-instance work-group count. */
 tdde_status tdde_launch_info(tdde_ctx* ctx, int32_t* n_wg, int32_t* wg_per_instance);
 

@@ -50,6 +50,18 @@ struct tdde_ctx {
   std::vector<int> block_of;
   int nblk = 0;
   bool prec_alloc = false;
+  int seg_min = 24;              // least rows per preconditioner segment (tdde_set_prec_segment)
+  // graph mode (tdde_set_graph): the launch sequence of a persistent chunk (two fill kernels and the
+  // cooperative solver launch) captured once per kernel variant and grid, replayed with the chunk's
+  // arguments written into the captured kernel nodes
+  bool use_graph = false;
+  struct Captured {
+    int v = -1, n_wg = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t solver = nullptr, zero_cnt = nullptr;
+  } cap;
+  size_t cap_lu = 0, cap_t = 0;  // allocated factor / boundary-matrix elements
   // workspace
   KVec<double> v64{};
   KVec<float> v32{};
@@ -277,6 +289,8 @@ tdde_status tdde_create(const tdde_dims* dims, void* hip_stream, tdde_ctx** out)
 
 tdde_status tdde_destroy(tdde_ctx* ctx) {
   if (!ctx) return TDDE_OK;
+  if (ctx->cap.exec) (void)hipGraphExecDestroy(ctx->cap.exec);
+  if (ctx->cap.graph) (void)hipGraphDestroy(ctx->cap.graph);
   for (void* p : ctx->allocs) (void)hipFree(p);
   delete ctx;
   return TDDE_OK;
@@ -575,6 +589,20 @@ tdde_status tdde_debug_read_marks(tdde_ctx* c, uint64_t* host, int32_t cap) {
   return TDDE_OK;
 }
 
+tdde_status tdde_set_graph(tdde_ctx* c, int32_t on) {
+  if (!c) return fail(c, TDDE_ERR_ARG, "null context");
+  c->use_graph = on != 0;
+  return TDDE_OK;
+}
+
+tdde_status tdde_set_prec_segment(tdde_ctx* c, int32_t min_rows) {
+  if (!c) return fail(c, TDDE_ERR_ARG, "null context");
+  if (min_rows < 2 * c->d.half_band + 1 || min_rows > 4096)
+    return fail(c, TDDE_ERR_ARG, "min_rows must be at least the factor band width (13) and at most 4096");
+  c->seg_min = min_rows;
+  return TDDE_OK;
+}
+
 tdde_status tdde_debug_set_shadow(tdde_ctx* c, const void* shadow) {
   if (!c) return fail(c, TDDE_ERR_ARG, "null context");
   c->shadow = static_cast<const double2*>(shadow);
@@ -770,7 +798,7 @@ tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
   // segments, so more of the factors stay resident in the Infinity Cache beside the solver's vectors
   // between two solves (hydrogen: 147 MB instead of 186 MB). Measured on the hydrogen step, 24 rows
   // beat 16, 32, 40 and 48 (longer segments lengthen each thread's substitution chain).
-  const int m = std::max({w, 24, (n + kMaxSeg - 1) / kMaxSeg});
+  const int m = std::max({w, c->seg_min, (n + kMaxSeg - 1) / kMaxSeg});
   const int P = (n + m - 1) / m;
   std::vector<cd> LU, TL, TU, CL, CU;
   const size_t tsz = (size_t)P * w * w;
@@ -798,7 +826,11 @@ tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
     std::copy(CU.begin(), CU.end(), allCU.begin() + bk * tsz);
   }
   tdde_status s;
-  if (!c->prec_alloc) {
+  if (!c->prec_alloc || allLU.size() > c->cap_lu || allTL.size() > c->cap_t) {
+    // first factorisation, or a segment length whose factors need more room (earlier buffers stay
+    // allocated until tdde_destroy)
+    c->cap_lu = allLU.size();
+    c->cap_t = allTL.size();
     if ((s = dev_alloc(c, (double2**)&c->pc64.LU, allLU.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (double2**)&c->pc64.TL, allTL.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (double2**)&c->pc64.TU, allTU.size())) != TDDE_OK) return s;
@@ -809,6 +841,8 @@ tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
     if ((s = dev_alloc(c, (float2**)&c->pc32.TU, allTU.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (float2**)&c->pc32.CL, allCL.size())) != TDDE_OK) return s;
     if ((s = dev_alloc(c, (float2**)&c->pc32.CU, allCU.size())) != TDDE_OK) return s;
+  }
+  if (!c->prec_alloc) {
     if ((s = upload(c, (int**)&c->pc64.block_of, c->block_of.data(), c->block_of.size())) != TDDE_OK) return s;
     c->pc32.block_of = c->pc64.block_of;
     const std::vector<int> order = chain_order_of(c->block_of, c->nblk);
@@ -949,6 +983,60 @@ static tdde_status check_opts(tdde_ctx* c, const tdde_solve_opts* o) {
   return TDDE_OK;
 }
 
+// Graph mode: capture [fill counters, fill barrier words, cooperative solver launch] on the
+// context's stream once per (variant, grid), then replay it with this chunk's arguments set on the
+// captured kernel nodes. Capture needs a stream other than the legacy default stream; a HIP error
+// on the way (a runtime that does not capture cooperative launches) is returned as TDDE_ERR_HIP
+// with its message.
+static tdde_status run_graph(tdde_ctx* c, SolveArgs& a, int v, int n_chunk) {
+  auto& cp = c->cap;
+  const int n_cnt = 64 * kCounterPerStep;  // the whole counter array (independent of n_chunk)
+  void* args[] = {&a};
+  if (cp.v != v || cp.n_wg != c->n_wg) {
+    if (cp.exec) { (void)hipGraphExecDestroy(cp.exec); cp.exec = nullptr; }
+    if (cp.graph) { (void)hipGraphDestroy(cp.graph); cp.graph = nullptr; }
+    cp.v = -1;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(c->counters), n_cnt);
+    hipLaunchKernelGGL(zero_words, dim3(8), dim3(256), 0, c->stream, c->bar, kBarWords);
+    const hipError_t el = hipLaunchCooperativeKernel(persistent_variant(v), dim3(c->n_wg), dim3(kThreads), args, 0,
+                                                     c->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+    if (el != hipSuccess || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(c, TDDE_ERR_HIP, std::string("graph capture of the cooperative launch: launch ") +
+                                       hipGetErrorString(el) + ", end capture " + hipGetErrorString(ee));
+    }
+    cp.graph = g;
+    size_t nn = 0;
+    HIP_TRY(c, hipGraphGetNodes(g, nullptr, &nn));
+    std::vector<hipGraphNode_t> nodes(nn);
+    HIP_TRY(c, hipGraphGetNodes(g, nodes.data(), &nn));
+    cp.solver = cp.zero_cnt = nullptr;
+    for (hipGraphNode_t nd : nodes) {
+      hipGraphNodeType ty;
+      HIP_TRY(c, hipGraphNodeGetType(nd, &ty));
+      if (ty != hipGraphNodeTypeKernel) continue;
+      hipKernelNodeParams kp{};
+      HIP_TRY(c, hipGraphKernelNodeGetParams(nd, &kp));
+      if (kp.func == persistent_variant(v)) cp.solver = nd;
+    }
+    if (!cp.solver) return fail(c, TDDE_ERR_HIP, "graph capture: the solver kernel node was not recorded");
+    HIP_TRY(c, hipGraphInstantiate(&cp.exec, g, nullptr, nullptr, 0));
+    cp.v = v;
+    cp.n_wg = c->n_wg;
+  } else {
+    hipKernelNodeParams kp{};
+    HIP_TRY(c, hipGraphKernelNodeGetParams(cp.solver, &kp));
+    kp.kernelParams = args;
+    HIP_TRY(c, hipGraphExecKernelNodeSetParams(cp.exec, cp.solver, &kp));
+  }
+  HIP_TRY(c, hipGraphLaunch(cp.exec, c->stream));
+  (void)n_chunk;
+  return TDDE_OK;
+}
+
 static tdde_status run_persistent(tdde_ctx* c, SolveArgs& a, int n_chunk) {
   if (n_chunk > 64) return fail(c, TDDE_ERR_ARG, "at most 64 steps per launch");
   const int v = 2 * (a.mixed ? 1 : 0) + (a.use_prec ? 1 : 0);
@@ -961,6 +1049,7 @@ static tdde_status run_persistent(tdde_ctx* c, SolveArgs& a, int n_chunk) {
   a.G = G;
   a.marks = c->marks;
   a.n_marks = c->n_marks;
+  if (c->use_graph && a.counters == c->counters && a.bar == c->bar && !c->marks) return run_graph(c, a, v, n_chunk);
   // barrier words and per-step counters start at zero (a fill kernel, so the call can be captured)
   hipLaunchKernelGGL(zero_words, dim3(64), dim3(256), 0, c->stream, reinterpret_cast<unsigned*>(a.counters),
                      n_chunk * kCounterPerStep);

@@ -376,9 +376,37 @@ def test_launch_shape_errors_and_autotune(gpu):
         scratch.copy_(psi0)
         s.run_batched(scratch, w.t0, 0, 8, np.array([8], dtype=np.int32), opts, stats)
 
-    best, times = tune_launch(s, run, reps=2)
-    assert set(times) == {1, 2, 3, 4} and best == min(times, key=times.get)
+    best, times, grids = tune_launch(s, run, reps=2)
+    assert set(times) == {1, 2, 3, 4} and times[best] == min(times.values())
+    assert s.launch_info()[0] == grids[best]
     torch.cuda.synchronize()
     st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
     assert np.all(st["status"] == 0)
     s.close()
+
+
+@pytest.mark.parametrize("seg", [16, 48])
+def test_prec_segment_lengths_match_oracle(gpu, seg):
+    """Other least segment lengths of the preconditioner (refactored at set_dt) give the same steps."""
+    P = _lib()
+    w = dkb.config2(nr=300, r_max=60.0, lmax=3, driven=True)
+    s = P.Solver(w.op, 1)
+    try:
+        with pytest.raises(P.TddeError):
+            s.set_prec_segment(5)
+        s.set_prec_segment(seg)
+        s.set_dt(w.dt)
+        s.set_pulses(w.pulses)
+        psi = _dev(w.psi0).reshape(-1)
+        st = torch.zeros(3 * 40, dtype=torch.uint8, device=DEV)
+        s.run_batched(psi, w.t0, 0, 3, np.array([3], dtype=np.int32),
+                      P.solve_opts(tol=1e-12, guess=P.GUESS_PREV, precond=1), st)
+        torch.cuda.synchronize()
+        got = psi.cpu().numpy().reshape(w.psi0[0].shape)
+    finally:
+        s.close()
+    asm = Assembled(w.op)
+    ref = w.psi0[0]
+    for k in range(3):
+        ref, _ = cn_step(asm, w.pulses[0], w.t0 + k * w.dt, w.dt, ref, solver="splu")
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
