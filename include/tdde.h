@@ -282,6 +282,21 @@ tdde_status tdde_set_graph(tdde_ctx* ctx, int32_t on);
  * at the next tdde_set_dt (which refactors). TDDE_ERR_ARG when min_rows < 13 or > 4096. */
 tdde_status tdde_set_prec_segment(tdde_ctx* ctx, int32_t min_rows);
 
+/* Solver form of time steps with the previous-state guess in FP64 (tdde_step, tdde_run_batched with
+ * guess TDDE_GUESS_PREV and precision TDDE_PREC_FP64): on = 0 (default) runs a call as one
+ * persistent cooperative launch; on = 1 runs every window of the BiCGSTAB iteration (van der Vorst
+ * 1992; the iteration of eq. solPsi, right preconditioner of eq. matrixM when enabled) as a kernel of
+ * its own, each at the occupancy its registers allow, with the scalar recurrence in device memory
+ * and every decision taken by the last work-group of the instance (deterministic sums). The same
+ * iteration, convergence tests, restarts and statistics as the persistent form; iterates agree to the
+ * solve tolerance (sums in another grouping). A call in this form returns when its steps are done:
+ * the host enqueues one iteration's kernels at a time and reads the count of unfinished instances one
+ * iteration behind (it cannot be captured into a graph). psi is the iterate itself. Other guess modes,
+ * mixed precision and tdde_solve keep the persistent form. Allocates the control blocks, partials and
+ * two ints of pinned host memory on the first call with on = 1. TDDE_ERR_STATE before tdde_assemble;
+ * TDDE_ERR_ARG for on outside {0, 1}. */
+tdde_status tdde_set_split(tdde_ctx* ctx, int32_t on);
+
 /* Persistent-grid size actually used (work-groups) and the per-instance work-group count. */
 tdde_status tdde_launch_info(tdde_ctx* ctx, int32_t* n_wg, int32_t* wg_per_instance);
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtdde.so")
 # (source, extra flags, object name): the persistent solver is compiled once per variant
-SOURCES = [("tdde.hip", [], "tdde"), ("mlp.hip", [], "mlp")] + [
+SOURCES = [("tdde.hip", [], "tdde"), ("mlp.hip", [], "mlp"), ("split.hip", [], "split")] + [
     ("persistent.hip", [f"-DTDDE_VARIANT={v}"], f"persistent_v{v}") for v in range(4)]
 ARCH = os.environ.get("TDDE_OFFLOAD_ARCH", "gfx950")
 

@@ -17,6 +17,7 @@
 
 #include "../../include/tdde.h"
 #include "solver.hpp"
+#include "split.hpp"
 
 using namespace tdde;
 using cd = std::complex<double>;
@@ -98,6 +99,15 @@ struct tdde_ctx {
   double* spec_grid = nullptr;    // [n_grid]
   double* spec_dens = nullptr;    // [batch][nang][max levels]
   double* spec_err = nullptr;     // [batch]
+  // kernel-per-window solver (tdde_set_split)
+  bool split = false;
+  int sp_G = 0;                   // work-groups per instance of its apply and vector kernels
+  SplitCtl* sp_ctl = nullptr;     // [batch] control blocks
+  int* sp_cnt = nullptr;          // [batch][kSpCntLine] arrival counters
+  double2* sp_part = nullptr;     // [batch][sp_G][kSpSlots]
+  int* sp_flag = nullptr;         // pinned host memory [2]: unfinished instances after a block
+  hipEvent_t sp_ev[2] = {nullptr, nullptr};
+  std::vector<int> ones;          // n_steps of a single step
 };
 
 // persistent kernel variants, index = 2 * mixed + preconditioned (each compiled in its own object
@@ -218,7 +228,8 @@ __global__ __launch_bounds__(kThreads) void apply_kernel(DevOp<T> op, const c2_t
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void precond_kernel(DevPrec<T> pc, int nr, const c2_t<T>* in, c2_t<T>* out, int E) {
+// two work-groups per CU: the chain solve fits 256 registers per lane without spills
+__global__ __launch_bounds__(kThreads, 2) void precond_kernel(DevPrec<T> pc, int nr, const c2_t<T>* in, c2_t<T>* out, int E) {
   __shared__ ChainLds<T> lds;
   const int j = pc.chain_order[blockIdx.x], b = blockIdx.y;
   if (j < 0) return;  // padding item (uniform over the work-group)
@@ -291,6 +302,9 @@ tdde_status tdde_destroy(tdde_ctx* ctx) {
   if (!ctx) return TDDE_OK;
   if (ctx->cap.exec) (void)hipGraphExecDestroy(ctx->cap.exec);
   if (ctx->cap.graph) (void)hipGraphDestroy(ctx->cap.graph);
+  for (hipEvent_t e : ctx->sp_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->sp_flag) (void)hipHostFree(ctx->sp_flag);
   for (void* p : ctx->allocs) (void)hipFree(p);
   delete ctx;
   return TDDE_OK;
@@ -603,6 +617,37 @@ tdde_status tdde_set_prec_segment(tdde_ctx* c, int32_t min_rows) {
   return TDDE_OK;
 }
 
+// Work-groups per instance of the kernel-per-window solver's apply and vector kernels: four per CU
+// over the batch (two rounds of the two-per-CU apply occupancy), a multiple of 8 so that work-group g
+// of every instance runs on XCD g % 8, and no more than the instance has tiles (rounded up to 8).
+static int split_wg(const tdde_ctx* c) {
+  const long tiles = (long)c->op64.nang * c->op64.n_itiles;
+  long g = (4L * c->ncu / c->d.batch) / 8 * 8;
+  g = std::max(8L, std::min(g, (tiles + 7) / 8 * 8));
+  return (int)g;
+}
+
+tdde_status tdde_set_split(tdde_ctx* c, int32_t on) {
+  if (!c) return fail(c, TDDE_ERR_ARG, "null context");
+  if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
+  if (on != 0 && on != 1) return fail(c, TDDE_ERR_ARG, "on must be 0 or 1");
+  if (on && !c->sp_ctl) {
+    const int G = split_wg(c);
+    const size_t B = (size_t)c->d.batch;
+    if ((double)B * G > 2.0e9) return fail(c, TDDE_ERR_ARG, "batch too large for the kernel-per-window grid");
+    tdde_status s;
+    if ((s = dev_alloc(c, &c->sp_ctl, B)) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, &c->sp_cnt, B * kSpCntLine)) != TDDE_OK) return s;
+    if ((s = dev_alloc(c, &c->sp_part, B * G * kSpSlots)) != TDDE_OK) return s;
+    HIP_TRY(c, hipHostMalloc(reinterpret_cast<void**>(&c->sp_flag), 2 * sizeof(int), hipHostMallocCoherent));
+    c->sp_flag[0] = c->sp_flag[1] = -1;
+    for (hipEvent_t& e : c->sp_ev) HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->sp_G = G;
+  }
+  c->split = on != 0;
+  return TDDE_OK;
+}
+
 tdde_status tdde_debug_set_shadow(tdde_ctx* c, const void* shadow) {
   if (!c) return fail(c, TDDE_ERR_ARG, "null context");
   c->shadow = static_cast<const double2*>(shadow);
@@ -629,8 +674,13 @@ tdde_status tdde_set_launch(tdde_ctx* c, int32_t wg_per_cu) {
 tdde_status tdde_launch_info(tdde_ctx* c, int32_t* n_wg, int32_t* per_inst) {
   if (!c || !n_wg || !per_inst) return fail(c, TDDE_ERR_ARG, "null argument");
   if (!c->assembled) return fail(c, TDDE_ERR_STATE, "assemble first");
-  *n_wg = c->n_wg;
-  *per_inst = c->G;
+  if (c->split) {
+    *n_wg = c->sp_G * c->d.batch;
+    *per_inst = c->sp_G;
+  } else {
+    *n_wg = c->n_wg;
+    *per_inst = c->G;
+  }
   return TDDE_OK;
 }
 
@@ -1106,11 +1156,11 @@ static_assert(sizeof(StatsDev) == sizeof(tdde_solve_stats) && offsetof(StatsDev,
               "device statistics must match the ABI struct");
 
 // Copy the statistics of a single-step launch to the host (synchronises the stream); bar: the
-// launch's grid-barrier words (time-out flag).
+// launch's grid-barrier words (time-out flag), null for the kernel-per-window solver.
 static tdde_status collect_stats(tdde_ctx* c, tdde_solve_stats* out, const StatsDev* stats_dev, const unsigned* bar) {
   HIP_TRY(c, hipMemcpyAsync(out, stats_dev, (size_t)c->d.batch * sizeof(StatsDev), hipMemcpyDeviceToHost, c->stream));
   unsigned err_word = 0;
-  HIP_TRY(c, hipMemcpyAsync(&err_word, bar + kBarErr, sizeof(err_word), hipMemcpyDeviceToHost, c->stream));
+  if (bar) HIP_TRY(c, hipMemcpyAsync(&err_word, bar + kBarErr, sizeof(err_word), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (err_word != 0) return fail(c, TDDE_ERR_HIP, "grid barrier timed out (work-groups not co-resident)");
   tdde_status worst = TDDE_OK;
@@ -1217,6 +1267,65 @@ tdde_status tdde_solve_static(tdde_ctx* c, const void* b, void* x, const tdde_so
   return collect_stats(c, stats, a.stats, a.bar);
 }
 
+// Time steps by the kernel-per-window solver: blocks of kernels (one BiCGSTAB iteration of every
+// unfinished instance each) are enqueued until the count of unfinished instances, read one block
+// behind from host memory, reaches zero. Returns when every instance has finished its steps of the
+// call (the stream then holds at most one block of kernels that find nothing to do).
+static tdde_status run_split(tdde_ctx* c, const SolveArgs& a) {
+  SplitArgs s{};
+  s.op = c->op64;
+  s.pc = c->pc64;
+  const KVec<double>& V = a.v64;
+  s.x = a.psi;
+  s.r = V.r;
+  s.rh = V.rh;
+  s.p = V.p;
+  s.ph = V.ph;
+  s.v = V.v;
+  s.s = V.s;
+  s.sh = V.sh;
+  s.t = V.t;
+  s.bvec[0] = c->bvec;
+  s.bvec[1] = c->bvec2;
+  s.part = c->sp_part;
+  s.ctl = c->sp_ctl;
+  s.cnt = c->sp_cnt;
+  s.stats = a.stats;
+  s.n_steps = a.n_steps;
+  s.pulses = a.pulses;
+  s.ftab = a.ftab;
+  s.ftab_rows = a.ftab_rows;
+  s.n_fields = a.n_fields;
+  s.host_flag = c->sp_flag;
+  s.B = c->d.batch;
+  s.E = c->E;
+  s.G = c->sp_G;
+  s.step0 = a.step0;
+  s.n_chunk = a.n_chunk;
+  s.max_iter = a.max_iter;
+  s.use_prec = a.use_prec;
+  s.tol = a.tol;
+  s.dt = a.dt;
+  s.t0 = a.t0;
+  // a step takes at most max_iter iterations, 21 restarts and one extra residual check, each at
+  // least one block
+  const long max_blocks = (long)a.n_chunk * ((long)a.max_iter + 24) + 4;
+  for (long m = 0;; ++m) {
+    HIP_TRY(c, split_launch_block(s, c->stream, (int)(m & 1), m == 0));
+    HIP_TRY(c, hipEventRecord(c->sp_ev[m & 1], c->stream));
+    if (m == 0) continue;
+    HIP_TRY(c, hipEventSynchronize(c->sp_ev[(m - 1) & 1]));
+    const int left = __atomic_load_n(c->sp_flag + ((m - 1) & 1), __ATOMIC_ACQUIRE);
+    if (left == 0) break;
+    if (m >= max_blocks) return fail(c, TDDE_ERR_HIP, "kernel-per-window solver did not finish its steps");
+  }
+  return TDDE_OK;
+}
+
+static bool split_serves(const tdde_ctx* c, const tdde_solve_opts* o) {
+  return c->split && o->guess == TDDE_GUESS_PREV && o->precision == TDDE_PREC_FP64;
+}
+
 tdde_status tdde_step(tdde_ctx* c, void* psi, double t, const void* guess, const tdde_solve_opts* o,
                       tdde_solve_stats* stats) {
   if (!c || !psi) return fail(c, TDDE_ERR_ARG, "null argument");
@@ -1232,6 +1341,15 @@ tdde_status tdde_step(tdde_ctx* c, void* psi, double t, const void* guess, const
   a.t0 = t;
   a.step0 = 0;
   a.n_steps = nullptr;
+  if (split_serves(c, o)) {
+    c->ones.assign((size_t)c->d.batch, 1);
+    HIP_TRY(c, hipMemcpyAsync(c->n_steps_dev, c->ones.data(), (size_t)c->d.batch * sizeof(int), hipMemcpyHostToDevice,
+                              c->stream));
+    a.n_steps = c->n_steps_dev;
+    if ((s = run_split(c, a)) != TDDE_OK) return s;
+    if (!stats) return TDDE_OK;
+    return collect_stats(c, stats, c->stats_dev, nullptr);
+  }
   if ((s = run_persistent(c, a, 1)) != TDDE_OK) return s;
   if (!stats) return TDDE_OK;
   return collect_stats(c, stats);
@@ -1264,6 +1382,7 @@ tdde_status tdde_run_batched(tdde_ctx* c, void* psi, double t0, int32_t step0, i
   a.n_steps = c->n_steps_dev;
   a.guess_in = (const double2*)guess;
   a.stats = (StatsDev*)stats_dev;
+  if (split_serves(c, o)) return run_split(c, a);
   return run_persistent(c, a, n_chunk);
 }
 
