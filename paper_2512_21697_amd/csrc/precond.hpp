@@ -44,12 +44,22 @@ template <typename T> struct DevPrec {
   const c2_t<T>* CU;       // [nblk][w][w][P] upper group products
 };
 
+// Steps of every segment staged through LDS at a time in the substitutions, and the row pitch of the
+// staging array (kMaxSeg + 2: the cooperative writes of 2 segments x 8 steps per 16 lanes hit 16
+// different 16-byte bank groups).
+constexpr int kStageRows = 8;
+constexpr int kStagePitch = kMaxSeg + 2;
+
 // LDS of one chain solve: the boundary window of every segment and the true boundary of every
-// segment group.
+// segment group (phase 2); during the substitutions the windows' space holds the staged steps.
 template <typename T> struct ChainLds {
-  c2_t<T> win[kMaxSeg][kPrecW];
+  union {
+    c2_t<T> win[kMaxSeg][kPrecW];
+    c2_t<T> stage[kStageRows][kStagePitch];
+  };
   c2_t<T> u[kMaxSegGroups][kPrecW];
 };
+static_assert(kStageRows * kStagePitch <= kMaxSeg * kPrecW, "staged steps must fit the windows' space");
 
 // Vector element of row q in the [s][i] layout of one channel.
 __device__ inline size_t prow(int q, int nr) { return (size_t)(q & 1) * nr + (q >> 1); }
@@ -68,9 +78,8 @@ template <typename T> struct ChainIO {
   double2 c1, c2;     // MODE_P: (beta, omega); MODE_S: (alpha, -)
 };
 
-// Rows a lane keeps in flight during a substitution: the operands of the next kChainAhead rows are
-// loaded before the current row is computed and its results stored, so the loads overlap the
-// arithmetic of the rows before them instead of one memory latency being paid per row.
+// Rows of factor operands a lane keeps in flight during a substitution: the factors of the next
+// kChainAhead rows are loaded before the current row is computed.
 #ifndef TDDE_CHAIN_AHEAD
 #define TDDE_CHAIN_AHEAD 1
 #endif
@@ -79,96 +88,110 @@ constexpr int kChainAhead = TDDE_CHAIN_AHEAD;
 // Substitution kinds: lower phase 1 (forms the input), lower phase 3, upper phase 1, upper phase 3.
 enum { SUB_L1 = 0, SUB_L3 = 1, SUB_U1 = 2, SUB_U3 = 3 };
 
-// Operands of one row: the factor entries (L row: W values; U row: 1/U(q,q) and W values) and the
-// raw vector values the right-hand side is formed from.
+// Factor entries of one row: L row: W values; U row: 1/U(q,q) and W values.
 template <typename T, int NC> struct RowOps {
   c2_t<T> c[NC];
-  c2_t<T> z0, z1, z2;
 };
 
-template <typename T, int KIND, int MODE, int NC>
-__device__ inline void row_fetch(RowOps<T, NC>& ro, const c2_t<T>* LU, const ChainIO<T>& io, int nr, int q, int t,
-                                 int P) {
-  const size_t e = prow(q, nr);
+// LU: the block's factors offset to the calling thread's segment (entry stride P); t: row of the segment.
+template <typename T, int KIND, int NC>
+__device__ inline void row_fetch(RowOps<T, NC>& ro, const c2_t<T>* LU, int t, int P) {
   const c2_t<T>* row = LU + ((size_t)t * kPrecStride + (KIND <= SUB_L3 ? 0 : kPrecW)) * P;
 #pragma unroll
   for (int k = 0; k < NC; ++k) ro.c[k] = gld(row + (size_t)k * P);
-  if (KIND == SUB_L1) {
-    if constexpr (MODE == MODE_P) { ro.z0 = gld(io.r + e); ro.z1 = gld(io.pz + e); ro.z2 = gld(io.v + e); }
-    else if constexpr (MODE == MODE_S) { ro.z0 = gld(io.r + e); ro.z2 = gld(io.v + e); }
-    else if constexpr (MODE == MODE_FRESH) { ro.z0 = gld(io.r + e); }
-    else { ro.z0 = gld(io.pz + e); }
-  } else if (KIND == SUB_L3) {
-    ro.z0 = gld(io.pz + e);  // the input formed (and stored) in phase 1
+}
+
+// Vector element of step u of segment p in a pass (lower passes walk rows o + u upwards, upper
+// passes rows o + len - 1 - u downwards), or -1 past the segment's rows.
+__device__ inline long step_elem(int p, int u, int m, int n, int nr, bool lower) {
+  const int o = p * m;
+  const int len = min(m, n - o);
+  if (u >= len) return -1;
+  return (long)prow(lower ? o + u : o + len - 1 - u, nr);
+}
+
+// Input of one row of a pass at vector element e, loaded by the cooperative staging:
+//   L1: MODE_P z = r + beta (p - omega v) (stored into p), MODE_S z = r - alpha v (stored into s),
+//       MODE_FRESH z = r (stored into p), MODE_IN / MODE_IN_S z = the input (not rewritten);
+//   L3: z again; U1, U3: y of the lower solve (in out).
+template <typename T, int KIND, int MODE>
+__device__ inline c2_t<T> stage_input(const ChainIO<T>& io, long e) {
+  if constexpr (KIND == SUB_L1) {
+    if constexpr (MODE == MODE_P) {
+      const c2_t<T> omega = cmk<T>((T)io.c2.x, (T)io.c2.y), beta = cmk<T>((T)io.c1.x, (T)io.c1.y);
+      const c2_t<T> z = cfma<T>(beta, csub<T>(gld(io.pz + e), cmul<T>(omega, gld(io.v + e))), gld(io.r + e));
+      gst(io.pz + e, z);
+      return z;
+    } else if constexpr (MODE == MODE_S) {
+      const c2_t<T> z = csub<T>(gld(io.r + e), cmul<T>(cmk<T>((T)io.c1.x, (T)io.c1.y), gld(io.v + e)));
+      gst(io.pz + e, z);
+      return z;
+    } else if constexpr (MODE == MODE_FRESH) {
+      const c2_t<T> z = gld(io.r + e);
+      gst(io.pz + e, z);
+      return z;
+    } else {
+      return gld(io.pz + e);
+    }
+  } else if constexpr (KIND == SUB_L3) {
+    return gld(io.pz + e);
   } else {
-    ro.z0 = gld(io.out + e);  // y of the lower solve (U1), or y overwritten by nothing yet (U3)
+    return gld(io.out + e);
   }
 }
 
-// Right-hand side value of a lower phase-1 row from its raw operands:
-//   MODE_P:  z = r + beta (p - omega v)   (BiCGSTAB direction update; z is stored into p)
-//   MODE_S:  z = r - alpha v              (BiCGSTAB half step;        z is stored into s)
-//   MODE_FRESH: z = r (stored into p); MODE_IN, MODE_IN_S: z = input (not rewritten)
-template <typename T, int MODE, int NC>
-__device__ inline c2_t<T> row_input(const RowOps<T, NC>& ro, const ChainIO<T>& io) {
-  if constexpr (MODE == MODE_P) {
-    const c2_t<T> omega = cmk<T>((T)io.c2.x, (T)io.c2.y), beta = cmk<T>((T)io.c1.x, (T)io.c1.y);
-    return cfma<T>(beta, csub<T>(ro.z1, cmul<T>(omega, ro.z2)), ro.z0);
-  } else if constexpr (MODE == MODE_S) {
-    return csub<T>(ro.z0, cmul<T>(cmk<T>((T)io.c1.x, (T)io.c1.y), ro.z2));
-  } else {
-    return ro.z0;
-  }
-}
-
-// One lane's substitution through its segment [o, o+len) from the window win.
+// One pass of substitutions, every lane through its segment (len rows) from the window win:
 //   lower (L1, L3): rows ascending, win[k] = y_{q-1-k}; y_q = z_q - sum_k L(q, q-1-k) win[k]
 //   upper (U1, U3): rows descending, win[k] = x_{q+1+k}; x_q = (y_q - sum_k U(q, q+1+k) win[k]) / U(q,q)
-// Phase 1 kinds keep only the window (L1 also stores the formed input and accumulates |z|^2);
-// phase 3 kinds write the result into io.out.
-// LU: the block's factors offset to the calling thread's segment (entry stride P).
-template <typename T, int KIND, int MODE, int W>
-__device__ inline void substitute(const c2_t<T>* LU, int P, const ChainIO<T>& io, int nr, int o, int len,
-                                  c2_t<T> (&win)[W], double& nrm2) {
+// The pass runs in chunks of kStageRows steps of every segment: the work-group loads the chunk's
+// inputs into LDS (consecutive lanes take consecutive rows of one segment, so a wave's loads are
+// runs of whole pieces instead of one element per segment m / 2 elements apart), every lane
+// substitutes its rows from LDS, and phase-3 kinds write their results back through LDS the same
+// way. Phase-1 kinds keep only the window. All threads call (barriers inside).
+template <typename T, int KIND, int MODE, int W, int D = kChainAhead>
+__device__ inline void substitute(const c2_t<T>* LU, int P, int m, int n, const ChainIO<T>& io, int nr, int len,
+                                  c2_t<T> (&win)[W], ChainLds<T>& L) {
   constexpr bool lower = KIND <= SUB_L3;
+  constexpr bool writes = KIND == SUB_L3 || KIND == SUB_U3;
   constexpr int NC = lower ? W : W + 1;
-  constexpr int D = kChainAhead;
+  constexpr int C = kStageRows;
+  static_assert(C % D == 0, "the steps of a chunk must be whole rounds of the lookahead");
+  const int p = threadIdx.x;
   RowOps<T, NC> ro[D];
 #pragma unroll
   for (int d = 0; d < D; ++d)
-    if (d < len) {
-      const int tt = lower ? d : len - 1 - d;
-      row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, o + tt, tt, P);
+    if (d < len) row_fetch<T, KIND, NC>(ro[d], LU, lower ? d : len - 1 - d, P);
+  for (int c0 = 0; c0 < m; c0 += C) {
+    __syncthreads();  // the previous chunk (or the caller's use of this LDS) is finished
+    for (int idx = threadIdx.x; idx < P * C; idx += kThreads) {
+      const int pp = idx / C, uu = idx - pp * C;
+      const long e = step_elem(pp, c0 + uu, m, n, nr, lower);
+      if (e >= 0) L.stage[uu][pp] = stage_input<T, KIND, MODE>(io, e);
     }
-  for (int t0 = 0; t0 < len; t0 += D) {
+    __syncthreads();
+    for (int u0 = 0; u0 < C; u0 += D) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int t = t0 + d;
-      if (t < len) {
-        const int q = lower ? o + t : o + len - 1 - t;
-        const size_t e = prow(q, nr);
-        c2_t<T> acc;
-        if (KIND == SUB_L1) {
-          acc = row_input<T, MODE, NC>(ro[d], io);
-          nrm2 += (double)acc.x * acc.x + (double)acc.y * acc.y;
-        } else {
-          acc = ro[d].z0;
+      for (int d = 0; d < D; ++d) {
+        const int uu = u0 + d, u = c0 + uu;
+        if (u < len) {
+          c2_t<T> acc = L.stage[uu][p];
+#pragma unroll
+          for (int k = 0; k < W; ++k) acc = csub<T>(acc, cmul<T>(ro[d].c[lower ? k : k + 1], win[k]));
+          if (!lower) acc = cmul<T>(acc, ro[d].c[0]);
+#pragma unroll
+          for (int k = W - 1; k > 0; --k) win[k] = win[k - 1];
+          win[0] = acc;
+          if (u + D < len) row_fetch<T, KIND, NC>(ro[d], LU, lower ? u + D : len - 1 - u - D, P);
+          if (writes) L.stage[uu][p] = acc;
         }
-        const c2_t<T> zin = acc;
-#pragma unroll
-        for (int k = 0; k < W; ++k) acc = csub<T>(acc, cmul<T>(ro[d].c[lower ? k : k + 1], win[k]));
-        if (!lower) acc = cmul<T>(acc, ro[d].c[0]);
-#pragma unroll
-        for (int k = W - 1; k > 0; --k) win[k] = win[k - 1];
-        win[0] = acc;
-        // loads of row t + D are issued before this row's stores, so waiting for them later does
-        // not wait for the stores
-        if (t + D < len) {
-          const int tt = lower ? t + D : len - 1 - t - D;
-          row_fetch<T, KIND, MODE, NC>(ro[d], LU, io, nr, o + tt, tt, P);
-        }
-        if (KIND == SUB_L1 && MODE != MODE_IN && MODE != MODE_IN_S) gst(io.pz + e, zin);
-        if (KIND == SUB_L3 || KIND == SUB_U3) gst(io.out + e, acc);
+      }
+    }
+    if (writes) {
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < P * C; idx += kThreads) {
+        const int pp = idx / C, uu = idx - pp * C;
+        const long e = step_elem(pp, c0 + uu, m, n, nr, lower);
+        if (e >= 0) gst(io.out + e, L.stage[uu][pp]);
       }
     }
   }
@@ -280,9 +303,10 @@ __device__ inline void true_window(const c2_t<T>* Cm, int P, int q, const ChainL
 }
 
 // Solve M_blk z = input for one channel with the whole work-group (all threads call it; one
-// segment per thread).
-template <typename T, int MODE>
-__device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int blk, int nr, const ChainIO<T>& io, ChainLds<T>& L) {
+// segment per thread). D: rows of factor operands a lane keeps in flight in the substitutions.
+template <typename T, int MODE, int D = kChainAhead>
+__device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int blk, int nr, const ChainIO<T>& io,
+                                                      ChainLds<T>& L) {
   constexpr int W = kPrecW;
   const int t = threadIdx.x;
   const int P = pc.P, m = pc.m, n = pc.n;
@@ -294,14 +318,13 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int 
   const c2_t<T>* CU = pc.CU + blk * tsz;
   const int o = t * m;
   const int len = t < P ? min(m, n - o) : 0;
-  double dummy = 0.0;
   c2_t<T> win[W], tw[W];
 
   // ---- lower solve, phase 1: local windows; tail t_p[c] = y[o + len - W + c] = win[W-1-c]
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_L1, MODE, W>(LU, P, io, nr, o, len, win, dummy);
-  __syncthreads();  // the previous solve's readers of L are done
+  substitute<T, SUB_L1, MODE, W, D>(LU, P, m, n, io, nr, len, win, L);
+  __syncthreads();  // every lane is done with the staged steps
   if (t < P) {
 #pragma unroll
     for (int c = 0; c < W; ++c) L.win[t][c] = win[W - 1 - c];
@@ -321,12 +344,12 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int 
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_L3, MODE, W>(LU, P, io, nr, o, len, win, dummy);
+  substitute<T, SUB_L3, MODE, W, D>(LU, P, m, n, io, nr, len, win, L);
 
   // ---- upper solve, phase 1: heads h_p[c] = x[o + c] = win[c] with zero incoming window
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_U1, MODE, W>(LU, P, io, nr, o, len, win, dummy);
+  substitute<T, SUB_U1, MODE, W, D>(LU, P, m, n, io, nr, len, win, L);
   __syncthreads();  // every thread has read its lower window
   if (t < P) {
 #pragma unroll
@@ -346,7 +369,7 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int 
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_U3, MODE, W>(LU, P, io, nr, o, len, win, dummy);
+  substitute<T, SUB_U3, MODE, W, D>(LU, P, m, n, io, nr, len, win, L);
 }
 
 }  // namespace tdde

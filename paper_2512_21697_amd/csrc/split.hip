@@ -176,6 +176,15 @@ __device__ inline void sp_begin_step(const SplitArgs& a, int b, SplitCtl& c, dou
 // ---- kernels
 
 constexpr int kSpWaves = 2;  // waves per SIMD asked of the apply and chain kernels (<= 256 registers)
+#ifndef TDDE_SPLIT_CHAIN_AHEAD
+#define TDDE_SPLIT_CHAIN_AHEAD 1
+#endif
+#ifndef TDDE_SPLIT_CHAIN_WAVES
+#define TDDE_SPLIT_CHAIN_WAVES 2
+#endif
+// rows of factor operands in flight per lane in the chain solves, and the waves per SIMD asked of them
+constexpr int kSpChainAhead = TDDE_SPLIT_CHAIN_AHEAD;
+constexpr int kSpChainWaves = TDDE_SPLIT_CHAIN_WAVES;
 
 __global__ void sp_begin_kernel(SplitArgs a) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,25 +250,35 @@ void sp_prologue_kernel(SplitArgs a) {
   }
 }
 
-// p = r (new cycle) or r + beta (p - omega v), p^ = K^-1 p: one chain work item per work-group.
-__global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(kSpWaves)))
+// Chain work item of a work-group (the channel order: channels of one factor block on one XCD): its
+// channel's inputs and outputs; false for a padding item.
+__device__ inline bool sp_item(const SplitArgs& a, int b, double2* in, double2* out, double2 c1, double2 c2,
+                               ChainIO<double>& io, int& blk) {
+  const int j = a.pc.chain_order[blockIdx.x];
+  if (j < 0) return false;
+  const size_t cb = (size_t)b * a.E + (size_t)j * 2 * a.op.nr;
+  io.r = a.r + cb;
+  io.v = a.v + cb;
+  io.pz = in + cb;
+  io.out = out + cb;
+  io.c1 = c1;
+  io.c2 = c2;
+  blk = a.pc.block_of[j];
+  return true;
+}
+
+// p = r (new cycle) or r + beta (p - omega v), p^ = K^-1 p: one channel per work-group.
+__global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(kSpChainWaves)))
 void sp_dir_chain_kernel(SplitArgs a) {
   __shared__ ChainLds<double> L;
   const int b = blockIdx.y;
   const SplitCtl c = a.ctl[b];
   if (c.state != SP_ACTIVE) return;
-  const int j = a.pc.chain_order[blockIdx.x];
-  if (j < 0) return;
-  const size_t cb = (size_t)b * a.E + (size_t)j * 2 * a.op.nr;
   ChainIO<double> io;
-  io.r = a.r + cb;
-  io.v = a.v + cb;
-  io.pz = a.p + cb;
-  io.out = a.ph + cb;
-  io.c1 = c.beta;
-  io.c2 = c.omega;
-  if (c.fresh) chain_solve<double, MODE_FRESH>(a.pc, a.pc.block_of[j], a.op.nr, io, L);
-  else chain_solve<double, MODE_P>(a.pc, a.pc.block_of[j], a.op.nr, io, L);
+  int blk = 0;
+  if (!sp_item(a, b, a.p, a.ph, c.beta, c.omega, io, blk)) return;
+  if (c.fresh) chain_solve<double, MODE_FRESH, kSpChainAhead>(a.pc, blk, a.op.nr, io, L);
+  else chain_solve<double, MODE_P, kSpChainAhead>(a.pc, blk, a.op.nr, io, L);
 }
 
 // Without the preconditioner: p = r or r + beta (p - omega v).
@@ -336,22 +355,16 @@ __global__ __launch_bounds__(kThreads) void sp_s_kernel(SplitArgs a) {
 }
 
 // s^ = K^-1 s.
-__global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(kSpWaves)))
+__global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(kSpChainWaves)))
 void sp_chain_s_kernel(SplitArgs a) {
   __shared__ ChainLds<double> L;
   const int b = blockIdx.y;
   const SplitCtl c = a.ctl[b];
   if (c.state != SP_ACTIVE) return;
-  const int j = a.pc.chain_order[blockIdx.x];
-  if (j < 0) return;
-  const size_t cb = (size_t)b * a.E + (size_t)j * 2 * a.op.nr;
   ChainIO<double> io;
-  io.r = a.r + cb;
-  io.v = a.v + cb;
-  io.pz = a.s + cb;
-  io.out = a.sh + cb;
-  io.c1 = io.c2 = c.alpha;
-  chain_solve<double, MODE_IN_S>(a.pc, a.pc.block_of[j], a.op.nr, io, L);
+  int blk = 0;
+  if (!sp_item(a, b, a.s, a.sh, c.alpha, c.alpha, io, blk)) return;
+  chain_solve<double, MODE_IN_S, kSpChainAhead>(a.pc, blk, a.op.nr, io, L);
 }
 
 // t = A s^, <t, s>, <t, t> -> omega.
