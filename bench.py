@@ -117,11 +117,11 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name, launch_key):
-    """HBM bytes per step of the persistent kernel from the committed rocprofv3 counter summary
-    ``profiles/persistent_kernel_<name>_counters.json``, or None when it is missing, was taken from
-    other kernel sources or under another launch shape."""
-    path = os.path.join(ROOT, "profiles", f"persistent_kernel_{name}_counters.json")
+def measured_traffic(name, launch_key, kernel="persistent_kernel"):
+    """HBM counters of a kernel from the committed rocprofv3 counter summary
+    ``profiles/<kernel>_<name>_counters.json``, or None when it is missing, was taken from other
+    kernel sources or under another launch shape."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{name}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -134,16 +134,19 @@ def measured_traffic(name, launch_key):
 # ------------------------------------------------------------------------------ GPU runs
 
 def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0, launch=0, info=None,
-                  segment=None):
-    """Run warmup + timed steps of one instance in persistent chunks.
+                  segment=None, form=None):
+    """Run warmup + timed steps of one instance in chunks of steps (one library call each).
 
     launch: work-groups per CU of the persistent grid (1..4, 0 = library default), or "auto" to
     let the autotuner time one chunk of steps (on a scratch copy of the state, before the warmup)
     under every shape and keep the fastest. segment: least rows per preconditioner segment (None =
-    library default), or "auto" to tune it the same way (preconditioned runs only). ``info`` (a dict)
-    receives the choices, the timings and the grid actually launched.
+    library default), or "auto" to tune it the same way (preconditioned runs only). form: solver form,
+    "persistent" (None: the library default), "split" (one kernel per window of the iteration; FP64
+    previous-state-guess steps only) or "auto" to time both on the tuning chunk. ``info`` (a dict)
+    receives the choices, the timings, the grid actually launched and, in the split form, the
+    durations of the timed region's apply kernel v = A p^ (HIP events on the library's stream).
     Returns (ms_per_step, stats array, [(kernel ms, steps) per launch], wall seconds, final state)."""
-    from paper_2512_21697_amd.autotune import tune_launch, tune_segment
+    from paper_2512_21697_amd.autotune import tune_form, tune_launch, tune_segment
     s = P.Solver(w.op, 1)
     try:
         if segment not in (None, "auto"):
@@ -174,6 +177,17 @@ def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precisio
             s.set_launch(int(launch))
             if info is not None:
                 info["wg_per_cu"] = int(launch) or DEFAULT_WG_PER_CU
+        split_ok = guess == P.GUESS_PREV and precision == 0
+        if form == "auto" and split_ok:
+            best_f, ftimes = tune_form(s, one_chunk)
+            if info is not None:
+                info["form"] = best_f
+                info["ms_per_chunk_by_form"] = {k: round(v * 1e3, 3) for k, v in ftimes.items()}
+        else:
+            s.set_split(form == "split" and split_ok)
+            if info is not None:
+                info["form"] = "split" if (form == "split" and split_ok) else "persistent"
+        is_split = info is not None and info.get("form") == "split"
         if segment == "auto" and precond:
             best_m, mtimes = tune_segment(s, w.dt, one_chunk, prefer=DEFAULT_SEGMENT)
             if info is not None:
@@ -195,6 +209,8 @@ def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precisio
             s.run_batched(psi, w.t0, k, n, n_steps, opts, stats[k * 40:(k + n) * 40])
             k += n
         torch.cuda.synchronize()
+        if is_split:
+            s.split_timing(8 * steps + 16)
         evs = []
         t0 = time.perf_counter()
         start = torch.cuda.Event(enable_timing=True)
@@ -214,6 +230,14 @@ def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precisio
         wall = time.perf_counter() - t0
         ms = start.elapsed_time(end)
         launches = [(a.elapsed_time(b), n) for a, b, n in evs]
+        if is_split:
+            d = s.read_split_timing()
+            s.split_timing(0)
+            # launches in blocks past the last step find no work and end at once
+            act = [x for x in d if x > 0.1 * max(d)] if d else []
+            info["apply_v_launches"] = len(d)
+            info["apply_v_active_launches"] = len(act)
+            info["apply_v_ms"] = float(np.mean(act)) if act else None
         st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE)
     finally:
         s.close()
@@ -234,10 +258,11 @@ def step_summary(w, ms, st, launches):
             "alg_GBps": bytes_step * per_launch / (kern_ms * 1e-3) / 1e9}
 
 
-def step_section(P, torch, w, steps, warmup, precond, guess=None, launch=0, label=""):
+def step_section(P, torch, w, steps, warmup, precond, guess=None, launch=0, label="", form="auto"):
     guess = P.GUESS_PREV if guess is None else guess
     info = {}
-    ms, st, launches, wall, psi = run_gpu_steps(P, torch, w, steps, warmup, precond, guess, launch=launch, info=info)
+    ms, st, launches, wall, psi = run_gpu_steps(P, torch, w, steps, warmup, precond, guess, launch=launch, info=info,
+                                                form=form)
     out = step_summary(w, ms, st, launches)
     out.update({"workload": label, "steps": steps, "precond": bool(precond),
                 "guess": {0: "zero", 1: "previous", 2: "given"}[guess], "launch": info})
@@ -557,6 +582,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=200, help="steps per training trajectory of the learned guess")
     ap.add_argument("--wg-per-cu", default="auto", help="persistent work-groups per CU (1..4, 0 = default), or auto")
     ap.add_argument("--segment", default="auto", help="least rows per preconditioner segment, or auto")
+    ap.add_argument("--form", default="auto", choices=("auto", "persistent", "split"),
+                    help="solver form of the headline: one persistent launch per chunk, one kernel per window of "
+                         "the iteration, or auto (time both)")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline run (profiling runs of a sub-line's kernel only; no value)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -586,18 +614,45 @@ def main():
     else:
         seg = args.segment if args.segment == "auto" else int(args.segment)
         ms_step, st, launches, wall, psi = run_gpu_steps(P, torch, w3, args.steps, args.warmup, precond=1,
-                                                         guess=P.GUESS_PREV, launch=launch, info=tuning, segment=seg)
+                                                         guess=P.GUESS_PREV, launch=launch, info=tuning, segment=seg,
+                                                         form=args.form)
         del psi
         head = step_summary(w3, ms_step, st, launches)
     _log(f"bench: headline {head}")
-    key = f"grid{tuning.get('n_wg')}_seg{tuning.get('segment_rows')}"
-    tr = measured_traffic("beyond_dipole", key)
+    split_form = tuning.get("form") == "split"
     traffic = None
     passes = None
-    if tr is not None and not args.no_headline:
-        per_step = (tr["fetch_kib_per_step"] * tr["fetch_scale"] + tr["write_kib_per_step"] * tr["write_scale"]) * 1024.0
-        traffic = per_step * head["steps_per_launch"]
-        passes = per_step / max(1.0, head["iters_per_step"]) / (w3.op.n_unknowns * 16)
+    E3 = w3.op.n_unknowns
+    if split_form:
+        # dominant kernel: the operator apply v = A p^ fused with <r^, v> (one of three applies a step)
+        rk = "sp_apply_v_kernel"
+        rk_bytes = apply_bytes(w3.op) + E3 * 16
+        rk_ms = tuning.get("apply_v_ms")
+        achieved = rk_bytes / (rk_ms * 1e-3) / 1e9 if rk_ms else None
+        tr = measured_traffic("beyond_dipole", f"grid{tuning.get('n_wg')}", kernel=rk)
+        if tr is not None and not args.no_headline:
+            traffic = (tr["fetch_kib_per_launch"] * tr["fetch_scale"] + tr["write_kib_per_launch"] * tr["write_scale"]) * 1024.0
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic, "kernel": rk,
+                "kernel_ms_per_launch": rk_ms, "launches_timed": tuning.get("apply_v_active_launches"),
+                "alg_bytes_per_launch": rk_bytes,
+                "step_alg_bytes": head["alg_bytes_per_step"],
+                "step_alg_GBps": head["alg_bytes_per_step"] / (ms_step * 1e-3) / 1e9 if ms_step else None,
+                "source_hash": source_hash()}
+    else:
+        key = f"grid{tuning.get('n_wg')}_seg{tuning.get('segment_rows')}"
+        tr = measured_traffic("beyond_dipole", key)
+        if tr is not None and not args.no_headline:
+            per_step = (tr["fetch_kib_per_step"] * tr["fetch_scale"] + tr["write_kib_per_step"] * tr["write_scale"]) * 1024.0
+            traffic = per_step * head["steps_per_launch"]
+            passes = per_step / max(1.0, head["iters_per_step"]) / (E3 * 16)
+        roof = {"bound": "hbm", "achieved": head["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": head["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "persistent_kernel", "kernel_ms_per_launch": head["kernel_ms_per_launch"],
+                "steps_per_launch": head["steps_per_launch"],
+                "alg_bytes_per_launch": head["alg_bytes_per_step"] * head["steps_per_launch"],
+                "alg_bytes_per_step": head["alg_bytes_per_step"],
+                "hbm_passes_per_iteration": passes, "source_hash": source_hash()}
     res = {
         "metric": "TDDE steps/s (beyond-dipole operator, preconditioned FP64 BiCGSTAB to 1e-12)",
         "value": head["steps_per_s"],
@@ -614,20 +669,14 @@ def main():
         "config": {"workload": "beyond-dipole single-GPU share: Nr=4000 (order 7), Nang=770 (l<=40, |mu|<=9/2), "
                                "six coupling terms |dl|<=2 mu'=mu+-1, N=6.16e6 complex128, dt=1e-3, "
                                "E0=0.05 sin^2 pulses at w=0.057 and w+-2pi/T (T=20) from t=T/4, tol 1e-12, "
-                               "block-LU preconditioner, previous-state guess",
+                               "block-LU preconditioner, previous-state guess; solver form and launch autotuned",
                    "batch": 1, "seq_len": None, "parallelism": "single GPU", "launch": tuning},
         "iters_per_step": head["iters_per_step"],
         "matvecs_per_step": head["matvecs_per_step"],
         "precond_solves_per_step": head["precond_solves_per_step"],
         "all_converged": head["all_converged"],
         "max_true_rel_res": head["max_true_rel_res"],
-        "roofline": {"bound": "hbm", "achieved": head["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["alg_GBps"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "persistent_kernel", "kernel_ms_per_launch": head["kernel_ms_per_launch"],
-                     "steps_per_launch": head["steps_per_launch"],
-                     "alg_bytes_per_launch": head["alg_bytes_per_step"] * head["steps_per_launch"],
-                     "alg_bytes_per_step": head["alg_bytes_per_step"],
-                     "hbm_passes_per_iteration": passes, "source_hash": source_hash()},
+        "roofline": roof,
     }
     sub = {}
     if "c3plain" in sections:

@@ -307,6 +307,15 @@ tdde_status tdde_launch_info(tdde_ctx* ctx, int32_t* n_wg, int32_t* wg_per_insta
 tdde_status tdde_debug_phase_marks(tdde_ctx* ctx, int32_t cap);
 tdde_status tdde_debug_read_marks(tdde_ctx* ctx, uint64_t* host, int32_t cap);
 
+/* Diagnostics of the kernel-per-window form (tdde_set_split): record a pair of HIP events on the
+ * context's stream around each of the next cap launches of its apply kernel v = A p^ (the operator
+ * apply fused with <r^, v>), so that its launch durations are measured on the stream it runs on;
+ * cap = 0 disables. tdde_debug_read_split_timing waits for the recorded events, writes the duration
+ * of each recorded launch in milliseconds (launches in blocks that found no work included: they end
+ * at once), returns their count in *n (at most cap_host) and starts a new recording. */
+tdde_status tdde_debug_split_timing(tdde_ctx* ctx, int32_t cap);
+tdde_status tdde_debug_read_split_timing(tdde_ctx* ctx, float* ms, int32_t cap_host, int32_t* n);
+
 /* Test hook (no passage of the paper: it drives the breakdown branch of the iteration): shadow
  * residual r^ of the first BiCGSTAB cycle of every later tdde_solve / tdde_solve_static, a device
  * complex128 array [batch][nang][2][nr] that must stay valid while those calls run (NULL restores

@@ -61,7 +61,7 @@ EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "td
            "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_solve_static", "tdde_step", "tdde_spectrum_setup", "tdde_spectrum",
            "tdde_spectrum_error", "tdde_run_batched", "tdde_destroy",
            "tdde_launch_info", "tdde_set_launch", "tdde_set_prec_segment", "tdde_set_split", "tdde_set_graph", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
-           "tdde_debug_read_marks", "tdde_debug_set_shadow", "tdde_mlp_create", "tdde_mlp_destroy",
+           "tdde_debug_read_marks", "tdde_debug_set_shadow", "tdde_debug_split_timing", "tdde_debug_read_split_timing", "tdde_mlp_create", "tdde_mlp_destroy",
            "tdde_mlp_param_count", "tdde_mlp_set_params", "tdde_mlp_get_params", "tdde_mlp_get_grads",
            "tdde_mlp_forward", "tdde_mlp_backward", "tdde_mlp_adam", "tdde_mlp_set_pulses", "tdde_mlp_guess",
            "tdde_mlp_last_error", "tdde_mlp_fit_skip", "tdde_mlp_set_skip", "tdde_mlp_get_skip"]
@@ -105,6 +105,8 @@ def load():
         "tdde_debug_phase_marks": [P, C.c_int32],
         "tdde_debug_read_marks": [P, P, C.c_int32],
         "tdde_debug_set_shadow": [P, P],
+        "tdde_debug_split_timing": [P, C.c_int32],
+        "tdde_debug_read_split_timing": [P, P, C.c_int32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -405,6 +407,18 @@ class Solver:
         """Kernel-per-window solver for FP64 steps with the previous-state guess (True), or one
         persistent launch per call (False, the default)."""
         self._check(self.lib.tdde_set_split(self.h, 1 if on else 0))
+
+    def split_timing(self, cap: int):
+        """Record the launch durations of the kernel-per-window form's apply kernel v = A p^ for the
+        next ``cap`` launches (0 disables)."""
+        self._check(self.lib.tdde_debug_split_timing(self.h, int(cap)))
+
+    def read_split_timing(self, cap: int = 65536):
+        """Durations (ms) of the recorded launches; starts a new recording."""
+        buf = (C.c_float * cap)()
+        n = C.c_int32()
+        self._check(self.lib.tdde_debug_read_split_timing(self.h, buf, cap, C.byref(n)))
+        return list(buf[:n.value])
 
     def launch_info(self):
         a, b = C.c_int32(), C.c_int32()

@@ -1,14 +1,16 @@
 """Autotuner for the solver's launch knobs.
 
-Two knobs are measured rather than fixed, because the best point depends on the operator size and the
+Three knobs are measured rather than fixed, because the best point depends on the operator size and the
 batch:
+  * the solver form: one persistent cooperative launch per chunk of steps, or one kernel per window of
+    the iteration (each at its own occupancy; pays a launch and a host read per iteration);
   * the persistent grid's shape (work-groups per CU): latency hiding (more waves in flight for the
     banded applies and the preconditioner's substitution chains) against the cost of the grid-wide
     barriers every work-group takes part in. Kernel variants cap the shape by their occupancy, so
     several requested shapes can launch the same grid; those are timed once.
   * the preconditioner's segment length (rows per thread of the segmented triangular solves):
     longer segments mean fewer boundary matrices but longer sequential chains.
-``tune_launch`` and ``tune_segment`` time a caller-supplied piece of work (one persistent chunk of
+``tune_launch``, ``tune_form`` and ``tune_segment`` time a caller-supplied piece of work (one persistent chunk of
 steps on a scratch copy of the state) under every candidate and leave the solver on the fastest.
 
 Host code here only selects and times; the work itself runs in the library.
@@ -108,4 +110,26 @@ def tune_segment(solver, dt: float, run: Callable[[], None], candidates: Iterabl
     best = _pick(times, prefer, margin)
     solver.set_prec_segment(best)
     solver.set_dt(dt)
+    return best, times
+
+
+def tune_form(solver, run: Callable[[], None], reps: int = 3, sync: Callable[[], None] = None,
+              prefer: str = None, margin: float = 0.02) -> Tuple[str, Dict[str, float]]:
+    """Time ``run()`` in the persistent form (on the solver's current launch shape) and in the
+    kernel-per-window form, and keep the faster (``prefer`` kept within ``margin``). Returns
+    (chosen form, {form: median seconds}); the solver is left on the chosen form."""
+    if sync is None:
+        import torch
+        sync = torch.cuda.synchronize
+    times: Dict[str, float] = {}
+    for form in ("persistent", "split"):
+        try:
+            solver.set_split(form == "split")
+        except TddeError:
+            continue
+        times[form] = _median_time(run, sync, reps)
+    if not times:
+        raise TddeError(-1, "no solver form accepted")
+    best = _pick(times, prefer, margin)
+    solver.set_split(best == "split")
     return best, times

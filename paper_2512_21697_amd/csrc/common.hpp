@@ -35,6 +35,12 @@ template <typename T> __device__ inline c2_t<T> cfma(c2_t<T> a, c2_t<T> b, c2_t<
   acc.y = fma(a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
   return acc;
 }
+// acc - a * b (complex a, complex b)
+template <typename T> __device__ inline c2_t<T> cfms(c2_t<T> a, c2_t<T> b, c2_t<T> acc) {
+  acc.x = fma(-a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(-a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
 // acc + r * b (real r)
 template <typename T> __device__ inline c2_t<T> rfma(T r, c2_t<T> b, c2_t<T> acc) {
   acc.x = fma(r, b.x, acc.x); acc.y = fma(r, b.y, acc.y);

@@ -15,6 +15,10 @@
 //      group boundaries with the precomputed group products C_p, and finally every window is
 //      corrected by C_p times the true boundary entering its group;
 //   3. every thread substitutes through its segment again from its true boundary window.
+// A work-group solves nc channels of one factor block at once (nc = 256 / P rounded down to a power of
+// two, at most 8): lane t = kk P + p runs segment p of channel kk, so the lanes of the nc channels read
+// the same factor rows, and phase 2 runs for all channels side by side (kSegGroup-segment groups of
+// every channel in their own slots).
 // Factor storage per block, row q = p m + t of segment p: entry k of the row is LU[t][k][p] (the
 // segment index fastest, so the threads of a wave read consecutive addresses), with entries
 // 0..w-1 = L(q, q-1-k), w = 1 / U(q, q), w+1+k = U(q, q+1+k); TL, TU [p][c][r] = T_p(r, c);
@@ -35,7 +39,8 @@ template <typename T> struct DevPrec {
   int m;                   // rows per segment (segments 0..P-2 have exactly m rows, m >= w)
   int P;                   // segments
   const int* block_of;     // [nang] factor block of channel j
-  const int* chain_order;  // [n_items] channel of chain work item w (-1: none), see chain_order_of
+  int nc;                  // channels of one block solved together by a work-group (1, 2, 4 or 8)
+  const int* chain_order;  // [n_items][nc] channels of chain work item w (-1: none), see chain_order_of
   int n_items;
   const c2_t<T>* LU;       // [nblk][m][kPrecStride][P]: entry k of row t of segment p
   const c2_t<T>* TL;       // [nblk][P][w][w] transposed per segment: TL[p][c][r] = T_p(r, c)
@@ -52,14 +57,25 @@ constexpr int kStagePitch = kMaxSeg + 2;
 
 // LDS of one chain solve: the boundary window of every segment and the true boundary of every
 // segment group (phase 2); during the substitutions the windows' space holds the staged steps.
+constexpr int kMaxChainNc = 8;  // channels of one work-group
+
 template <typename T> struct ChainLds {
   union {
     c2_t<T> win[kMaxSeg][kPrecW];
     c2_t<T> stage[kStageRows][kStagePitch];
   };
   c2_t<T> u[kMaxSegGroups][kPrecW];
+  long coff[kMaxChainNc];  // element offset of every channel of the work item within the instance
 };
 static_assert(kStageRows * kStagePitch <= kMaxSeg * kPrecW, "staged steps must fit the windows' space");
+
+// Channels of chain work item w (pc.chain_order row): count of valid entries (0 for a padding item).
+template <typename T> __device__ inline int chain_item(const DevPrec<T>& pc, int w, const int*& js) {
+  js = pc.chain_order + (size_t)w * pc.nc;
+  int nk = 0;
+  while (nk < pc.nc && js[nk] >= 0) ++nk;
+  return nk;
+}
 
 // Vector element of row q in the [s][i] layout of one channel.
 __device__ inline size_t prow(int q, int nr) { return (size_t)(q & 1) * nr + (q >> 1); }
@@ -71,10 +87,10 @@ __device__ inline size_t prow(int q, int nr) { return (size_t)(q & 1) * nr + (q 
 enum { MODE_P = 0, MODE_S = 1, MODE_IN = 2, MODE_FRESH = 3 /* z = r, stored into p */, MODE_IN_S = 4 /* z = s */ };
 
 template <typename T> struct ChainIO {
-  const c2_t<T>* r;   // residual (channel base)
-  c2_t<T>* pz;        // p or s vector (channel base); input for MODE_IN
-  const c2_t<T>* v;   // v (channel base)
-  c2_t<T>* out;       // preconditioned result (channel base)
+  const c2_t<T>* r;   // residual (instance base)
+  c2_t<T>* pz;        // p or s vector (instance base); input for MODE_IN
+  const c2_t<T>* v;   // v (instance base)
+  c2_t<T>* out;       // preconditioned result (instance base)
   double2 c1, c2;     // MODE_P: (beta, omega); MODE_S: (alpha, -)
 };
 
@@ -84,6 +100,7 @@ template <typename T> struct ChainIO {
 #define TDDE_CHAIN_AHEAD 1
 #endif
 constexpr int kChainAhead = TDDE_CHAIN_AHEAD;
+
 
 // Substitution kinds: lower phase 1 (forms the input), lower phase 3, upper phase 1, upper phase 3.
 enum { SUB_L1 = 0, SUB_L3 = 1, SUB_U1 = 2, SUB_U3 = 3 };
@@ -143,30 +160,38 @@ __device__ inline c2_t<T> stage_input(const ChainIO<T>& io, long e) {
 // One pass of substitutions, every lane through its segment (len rows) from the window win:
 //   lower (L1, L3): rows ascending, win[k] = y_{q-1-k}; y_q = z_q - sum_k L(q, q-1-k) win[k]
 //   upper (U1, U3): rows descending, win[k] = x_{q+1+k}; x_q = (y_q - sum_k U(q, q+1+k) win[k]) / U(q,q)
-// The pass runs in chunks of kStageRows steps of every segment: the work-group loads the chunk's
-// inputs into LDS (consecutive lanes take consecutive rows of one segment, so a wave's loads are
-// runs of whole pieces instead of one element per segment m / 2 elements apart), every lane
-// substitutes its rows from LDS, and phase-3 kinds write their results back through LDS the same
-// way. Phase-1 kinds keep only the window. All threads call (barriers inside).
+// The pass runs in chunks of kStageRows steps of every segment of the nk channels: the work-group
+// loads the chunk's inputs into LDS (consecutive threads take consecutive rows of one segment, so a
+// wave's loads are runs of whole pieces instead of one element per segment m / 2 elements apart),
+// every lane substitutes its rows from LDS, and phase-3 kinds write their results back through LDS
+// the same way. Phase-1 kinds keep only the window. All threads call (barriers inside).
 template <typename T, int KIND, int MODE, int W, int D = kChainAhead>
-__device__ inline void substitute(const c2_t<T>* LU, int P, int m, int n, const ChainIO<T>& io, int nr, int len,
-                                  c2_t<T> (&win)[W], ChainLds<T>& L) {
+__device__ inline void substitute(const c2_t<T>* LU, int P, int m, int n, int nk, const ChainIO<T>& io, int nr,
+                                  int len, c2_t<T> (&win)[W], ChainLds<T>& L) {
   constexpr bool lower = KIND <= SUB_L3;
   constexpr bool writes = KIND == SUB_L3 || KIND == SUB_U3;
   constexpr int NC = lower ? W : W + 1;
   constexpr int C = kStageRows;
   static_assert(C % D == 0, "the steps of a chunk must be whole rounds of the lookahead");
-  const int p = threadIdx.x;
+  const int lane = threadIdx.x;
+  const int nl = nk * P;  // lanes with a segment
   RowOps<T, NC> ro[D];
 #pragma unroll
   for (int d = 0; d < D; ++d)
     if (d < len) row_fetch<T, KIND, NC>(ro[d], LU, lower ? d : len - 1 - d, P);
+  auto elem = [&](int idx, int c0, int& uu) {
+    const int ln = idx / C;
+    uu = idx - ln * C;
+    const int kk = ln / P;
+    const long e = step_elem(ln - kk * P, c0 + uu, m, n, nr, lower);
+    return e >= 0 ? L.coff[kk] + e : -1L;
+  };
   for (int c0 = 0; c0 < m; c0 += C) {
     __syncthreads();  // the previous chunk (or the caller's use of this LDS) is finished
-    for (int idx = threadIdx.x; idx < P * C; idx += kThreads) {
-      const int pp = idx / C, uu = idx - pp * C;
-      const long e = step_elem(pp, c0 + uu, m, n, nr, lower);
-      if (e >= 0) L.stage[uu][pp] = stage_input<T, KIND, MODE>(io, e);
+    for (int idx = threadIdx.x; idx < nl * C; idx += kThreads) {
+      int uu;
+      const long e = elem(idx, c0, uu);
+      if (e >= 0) L.stage[uu][idx / C] = stage_input<T, KIND, MODE>(io, e);
     }
     __syncthreads();
     for (int u0 = 0; u0 < C; u0 += D) {
@@ -174,24 +199,24 @@ __device__ inline void substitute(const c2_t<T>* LU, int P, int m, int n, const 
       for (int d = 0; d < D; ++d) {
         const int uu = u0 + d, u = c0 + uu;
         if (u < len) {
-          c2_t<T> acc = L.stage[uu][p];
+          c2_t<T> acc = L.stage[uu][lane];
 #pragma unroll
-          for (int k = 0; k < W; ++k) acc = csub<T>(acc, cmul<T>(ro[d].c[lower ? k : k + 1], win[k]));
+          for (int k = 0; k < W; ++k) acc = cfms<T>(ro[d].c[lower ? k : k + 1], win[k], acc);
           if (!lower) acc = cmul<T>(acc, ro[d].c[0]);
 #pragma unroll
           for (int k = W - 1; k > 0; --k) win[k] = win[k - 1];
           win[0] = acc;
           if (u + D < len) row_fetch<T, KIND, NC>(ro[d], LU, lower ? u + D : len - 1 - u - D, P);
-          if (writes) L.stage[uu][p] = acc;
+          if (writes) L.stage[uu][lane] = acc;
         }
       }
     }
     if (writes) {
       __syncthreads();
-      for (int idx = threadIdx.x; idx < P * C; idx += kThreads) {
-        const int pp = idx / C, uu = idx - pp * C;
-        const long e = step_elem(pp, c0 + uu, m, n, nr, lower);
-        if (e >= 0) gst(io.out + e, L.stage[uu][pp]);
+      for (int idx = threadIdx.x; idx < nl * C; idx += kThreads) {
+        int uu;
+        const long e = elem(idx, c0, uu);
+        if (e >= 0) gst(io.out + e, L.stage[uu][idx / C]);
       }
     }
   }
@@ -205,18 +230,21 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Phase 2, first level: the recurrence inside every group of kSegGroup segments, started from the
-// group's own zero-window tail. Wave v owns groups 4v .. 4v+3; lane 13 k + r (k < 4) owns row r of
-// group 4v + k. The T row of the next step is loaded one step ahead.
+// Phase 2, first level: the recurrence inside every group of kSegGroup segments of every channel,
+// started from the group's own zero-window tail. Channel kk's groups occupy slots kk * GS .. kk * GS +
+// GS - 1 (GS = kMaxSegGroups / nc); wave v owns slots 4v .. 4v+3 and lane 13 k + r (k < 4) row r of
+// slot 4v + k. The T row of the next step is loaded one step ahead.
 //   lower: t_p = g_p - T_p t_{p-1}, p ascending from the group's first segment;
 //   upper: h_p = g_p - T_p h_{p+1}, p descending from the group's last segment.
 template <typename T, bool LOWER, int W>
-__device__ inline void group_recurrence(const c2_t<T>* Tm, int P, ChainLds<T>& L) {
+__device__ inline void group_recurrence(const c2_t<T>* Tm, int P, int nc, int nk, ChainLds<T>& L) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = lane / W, r = lane - k * W;
-  const int g = wave * 4 + k;
+  const int slot = wave * 4 + k, GS = kMaxSegGroups / nc;
+  const int kk = slot / GS, g = slot - kk * GS;
   const int lo = g * kSegGroup, hi = min(lo + kSegGroup - 1, P - 1);
-  const bool act = lane < 4 * W && lo < P;
+  const bool act = lane < 4 * W && kk < nk && lo < P;
+  const int base = kk * P;  // lane of the channel's segment 0
   c2_t<T> tr[W];
   auto fetch = [&](int step) {
     const int p = LOWER ? lo + step : hi - step;
@@ -232,29 +260,31 @@ __device__ inline void group_recurrence(const c2_t<T>* Tm, int P, ChainLds<T>& L
     c2_t<T> acc = cmk<T>(0, 0);
     if (on) {
       const int prev = LOWER ? p - 1 : p + 1;
-      acc = L.win[p][r];
+      acc = L.win[base + p][r];
 #pragma unroll
-      for (int c = 0; c < W; ++c) acc = csub<T>(acc, cmul<T>(tr[c], L.win[prev][c]));
+      for (int c = 0; c < W; ++c) acc = cfms<T>(tr[c], L.win[base + prev][c], acc);
     }
     fetch(step + 1);
     wave_sync();
-    if (on) L.win[p][r] = acc;
+    if (on) L.win[base + p][r] = acc;
     wave_sync();
   }
 }
 
-// Phase 2, second level (wave 0, lanes r < W): the true boundary of every group, in order,
+// Phase 2, second level (16 threads per channel, rows r < W, channel kk = thread / 16): the true
+// boundary of every group of the channel, in order,
 //   lower: u_0 = t_hi(0), u_G = t^loc_hi(G) + CL_hi(G) u_{G-1};
 //   upper: u_last = h_lo(last), u_G = h^loc_lo(G) + CU_lo(G) u_{G+1}.
 template <typename T, bool LOWER, int W>
-__device__ inline void group_boundaries(const c2_t<T>* Cm, int P, ChainLds<T>& L) {
-  const int r = threadIdx.x;
-  if (r >= W) return;
+__device__ inline void group_boundaries(const c2_t<T>* Cm, int P, int nc, int nk, ChainLds<T>& L) {
+  const int kk = threadIdx.x >> 4, r = threadIdx.x & 15;
+  if (kk >= nk || r >= W) return;
   const int NG = (P + kSegGroup - 1) / kSegGroup;
+  const int base = kk * P, us = kk * (kMaxSegGroups / nc);  // channel's first lane, first group slot
   const size_t cs = (size_t)P;  // stride between (row, column) planes of C
   auto seg_of = [&](int G) { return LOWER ? min(G * kSegGroup + kSegGroup - 1, P - 1) : G * kSegGroup; };
   const int G0 = LOWER ? 0 : NG - 1;
-  L.u[G0][r] = L.win[seg_of(G0)][r];
+  L.u[us + G0][r] = L.win[base + seg_of(G0)][r];
   c2_t<T> cr[W];
   auto fetch = [&](int G) {
     if (G >= 0 && G < NG && G != G0) {
@@ -268,27 +298,28 @@ __device__ inline void group_boundaries(const c2_t<T>* Cm, int P, ChainLds<T>& L
     const int G = LOWER ? step : NG - 1 - step;
     const int Gin = LOWER ? G - 1 : G + 1;
     wave_sync();
-    c2_t<T> acc = L.win[seg_of(G)][r];
+    c2_t<T> acc = L.win[base + seg_of(G)][r];
 #pragma unroll
-    for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(cr[c], L.u[Gin][c]));
+    for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(cr[c], L.u[us + Gin][c]));
     fetch(LOWER ? G + 1 : G - 1);
     wave_sync();
-    L.u[G][r] = acc;
+    L.u[us + G][r] = acc;
   }
 }
 
-// True boundary window of segment q into out[W]: the group-local window corrected by the group
-// product times the true boundary entering the group (nothing to correct in the group where the
-// recurrence starts).
+// True boundary window of segment q of channel kk into out[W]: the group-local window corrected by
+// the group product times the true boundary entering the group (nothing to correct in the group where
+// the recurrence starts).
 template <typename T, bool LOWER, int W>
-__device__ inline void true_window(const c2_t<T>* Cm, int P, int q, const ChainLds<T>& L, c2_t<T> (&out)[W]) {
+__device__ inline void true_window(const c2_t<T>* Cm, int P, int nc, int kk, int q, const ChainLds<T>& L,
+                                   c2_t<T> (&out)[W]) {
   const int NG = (P + kSegGroup - 1) / kSegGroup;
   const int G = q / kSegGroup;
 #pragma unroll
-  for (int c = 0; c < W; ++c) out[c] = L.win[q][c];
+  for (int c = 0; c < W; ++c) out[c] = L.win[kk * P + q][c];
   const bool corr = LOWER ? G > 0 : G < NG - 1;
   if (corr) {
-    const c2_t<T>* ub = L.u[LOWER ? G - 1 : G + 1];
+    const c2_t<T>* ub = L.u[kk * (kMaxSegGroups / nc) + (LOWER ? G - 1 : G + 1)];
     c2_t<T> uu[W];
 #pragma unroll
     for (int c = 0; c < W; ++c) uu[c] = ub[c];
@@ -302,74 +333,78 @@ __device__ inline void true_window(const c2_t<T>* Cm, int P, int q, const ChainL
   }
 }
 
-// Solve M_blk z = input for one channel with the whole work-group (all threads call it; one
-// segment per thread). D: rows of factor operands a lane keeps in flight in the substitutions.
+// Solve M_blk z = input for the channels js[0 .. nk) (nk <= pc.nc) of factor block blk with the whole
+// work-group (all threads call it). io holds the instance's vectors; D: rows of factor operands a lane
+// keeps in flight in the substitutions.
 template <typename T, int MODE, int D = kChainAhead>
 __device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int blk, int nr, const ChainIO<T>& io,
-                                                      ChainLds<T>& L) {
+                                                      const int* js, int nk, ChainLds<T>& L) {
   constexpr int W = kPrecW;
   const int t = threadIdx.x;
-  const int P = pc.P, m = pc.m, n = pc.n;
-  const c2_t<T>* LU = pc.LU + (size_t)blk * m * kPrecStride * P + (t < P ? t : 0);
+  const int P = pc.P, m = pc.m, n = pc.n, nc = pc.nc;
+  const int kk = t / P, p = t - kk * P;  // channel slot and segment of this lane
+  const bool on = kk < nk;
+  const c2_t<T>* LU = pc.LU + (size_t)blk * m * kPrecStride * P + (on ? p : 0);
   const size_t tsz = (size_t)P * W * W;
   const c2_t<T>* TL = pc.TL + blk * tsz;
   const c2_t<T>* TU = pc.TU + blk * tsz;
   const c2_t<T>* CL = pc.CL + blk * tsz;
   const c2_t<T>* CU = pc.CU + blk * tsz;
-  const int o = t * m;
-  const int len = t < P ? min(m, n - o) : 0;
+  const int len = on ? min(m, n - p * m) : 0;
   c2_t<T> win[W], tw[W];
+  __syncthreads();  // a previous solve of this work-group has finished with coff
+  if (t < nk) L.coff[t] = (long)js[t] * 2 * nr;  // read after the first substitution's barrier
 
   // ---- lower solve, phase 1: local windows; tail t_p[c] = y[o + len - W + c] = win[W-1-c]
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_L1, MODE, W, D>(LU, P, m, n, io, nr, len, win, L);
+  substitute<T, SUB_L1, MODE, W, D>(LU, P, m, n, nk, io, nr, len, win, L);
   __syncthreads();  // every lane is done with the staged steps
-  if (t < P) {
+  if (on) {
 #pragma unroll
     for (int c = 0; c < W; ++c) L.win[t][c] = win[W - 1 - c];
   }
   __syncthreads();
   // ---- phase 2: group recurrences, group boundaries
-  group_recurrence<T, true, W>(TL, P, L);
+  group_recurrence<T, true, W>(TL, P, nc, nk, L);
   __syncthreads();
-  group_boundaries<T, true, W>(CL, P, L);
+  group_boundaries<T, true, W>(CL, P, nc, nk, L);
   __syncthreads();
   // ---- phase 3: final substitution from the true window win[k] = y_{o-1-k} = t_{p-1}[W-1-k]
-  if (t > 0 && t < P) {
-    true_window<T, true, W>(CL, P, t - 1, L, tw);
+  if (on && p > 0) {
+    true_window<T, true, W>(CL, P, nc, kk, p - 1, L, tw);
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = tw[W - 1 - k];
   } else {
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_L3, MODE, W, D>(LU, P, m, n, io, nr, len, win, L);
+  substitute<T, SUB_L3, MODE, W, D>(LU, P, m, n, nk, io, nr, len, win, L);
 
   // ---- upper solve, phase 1: heads h_p[c] = x[o + c] = win[c] with zero incoming window
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_U1, MODE, W, D>(LU, P, m, n, io, nr, len, win, L);
+  substitute<T, SUB_U1, MODE, W, D>(LU, P, m, n, nk, io, nr, len, win, L);
   __syncthreads();  // every thread has read its lower window
-  if (t < P) {
+  if (on) {
 #pragma unroll
     for (int c = 0; c < W; ++c) L.win[t][c] = win[c];
   }
   __syncthreads();
-  group_recurrence<T, false, W>(TU, P, L);
+  group_recurrence<T, false, W>(TU, P, nc, nk, L);
   __syncthreads();
-  group_boundaries<T, false, W>(CU, P, L);
+  group_boundaries<T, false, W>(CU, P, nc, nk, L);
   __syncthreads();
   // ---- phase 3: x from the true incoming window win[k] = x_{o+len+k} = h_{p+1}[k]
-  if (t + 1 < P) {
-    true_window<T, false, W>(CU, P, t + 1, L, tw);
+  if (on && p + 1 < P) {
+    true_window<T, false, W>(CU, P, nc, kk, p + 1, L, tw);
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = tw[k];
   } else {
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_U3, MODE, W, D>(LU, P, m, n, io, nr, len, win, L);
+  substitute<T, SUB_U3, MODE, W, D>(LU, P, m, n, nk, io, nr, len, win, L);
 }
 
 }  // namespace tdde

@@ -184,12 +184,12 @@ template <typename T> __device__ inline long tile_elem(const DevOp<T>& op, int j
   return tile_elem(op.nr, j, i0 / kTileR);
 }
 
-// Chain loop: channel j of the instance handled by work-group (j % G).
-// Work item w of the chain order (channels grouped by factor block, each block on one XCD) is taken
-// by work-group w mod G; items without a channel (-1) pad the order to whole rounds.
+// Chain loop: work item w of the chain order (the channels of one factor block solved together,
+// items of one block on one XCD) is taken by work-group w mod G; padding items have no channel.
 #define FOR_CHAINS(pc, wi)                                                   \
   for (int w_ = (wi).g; w_ < (pc).n_items; w_ += (wi).G)                   \
-    for (int j_ = (pc).chain_order[w_], once_ = 1; once_ && j_ >= 0; once_ = 0)
+    for (const int* js_ = (pc).chain_order + (size_t)w_ * (pc).nc; js_ != nullptr; js_ = nullptr)       \
+      for (int nk_ = chain_item(pc, w_, js_), once_ = 1; once_ && nk_ > 0; once_ = 0)
 
 template <typename T>
 __device__ inline c2_t<T> load_c(const c2_t<T>* p, long e) { return p[e]; }
@@ -235,24 +235,23 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
 }
 __device__ inline double2 dmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
-// Preconditioner chain phase for own channels (MODE_P / MODE_FRESH / MODE_IN_S); the whole
-// work-group solves one channel at a time.
+// Preconditioner chain phase for own work items (MODE_P / MODE_FRESH / MODE_IN_S); the whole
+// work-group solves one item (the channels of one factor block) at a time.
 template <typename T, int MODE>
 __device__ inline void chains_own(const SolveArgs& a, const WgInfo& wi, const KVec<T>& V, size_t base, double2 c1,
                                   double2 c2, Shared& sh) {
   const DevOp<T>& op = op_of<T>(a);
   const DevPrec<T>& pc = pc_of<T>(a);
   FOR_CHAINS(pc, wi) {
-    const size_t cb = base + (size_t)j_ * 2 * op.nr;
     ChainIO<T> io;
-    io.r = V.r + cb;
-    io.v = V.v + cb;
+    io.r = V.r + base;
+    io.v = V.v + base;
     constexpr bool on_s = MODE == MODE_S || MODE == MODE_IN_S;
-    io.pz = (on_s ? V.s : V.p) + cb;
-    io.out = (on_s ? V.sh : V.ph) + cb;
+    io.pz = (on_s ? V.s : V.p) + base;
+    io.out = (on_s ? V.sh : V.ph) + base;
     io.c1 = c1;
     io.c2 = c2;
-    chain_solve<T, MODE>(pc, pc.block_of[j_], op.nr, io, lds_of<T>(sh).chain);
+    chain_solve<T, MODE>(pc, pc.block_of[js_[0]], op.nr, io, js_, nk_, lds_of<T>(sh).chain);
   }
 }
 

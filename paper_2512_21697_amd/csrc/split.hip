@@ -7,6 +7,30 @@ namespace tdde {
 
 namespace {
 
+// Launch-shape constants (compile-time knobs).
+#ifndef TDDE_SPLIT_APPLY_WAVES
+#define TDDE_SPLIT_APPLY_WAVES 2
+#endif
+#ifndef TDDE_SPLIT_GB
+#define TDDE_SPLIT_GB kGatherBatch
+#endif
+#ifndef TDDE_SPLIT_TR
+#define TDDE_SPLIT_TR 1
+#endif
+// waves per SIMD asked of the apply kernels, their gather batch and coupling terms per tap round
+constexpr int kSpWaves = TDDE_SPLIT_APPLY_WAVES;
+constexpr int kSpGB = TDDE_SPLIT_GB;
+constexpr int kSpTR = TDDE_SPLIT_TR;
+#ifndef TDDE_SPLIT_CHAIN_AHEAD
+#define TDDE_SPLIT_CHAIN_AHEAD 1
+#endif
+#ifndef TDDE_SPLIT_CHAIN_WAVES
+#define TDDE_SPLIT_CHAIN_WAVES 2
+#endif
+// rows of factor operands in flight per lane in the chain solves, and the waves per SIMD asked of them
+constexpr int kSpChainAhead = TDDE_SPLIT_CHAIN_AHEAD;
+constexpr int kSpChainWaves = TDDE_SPLIT_CHAIN_WAVES;
+
 // Work-group -> (instance b, work-group g of the instance) for the apply and vector kernels of a
 // B x G grid: w = 8 (B q + b) + x with g = 8 q + x, so work-group g of every instance runs on XCD
 // g % 8 and takes tiles t = g, g + G, ... (tile_coords: a radial tile of all channels on one XCD).
@@ -85,7 +109,7 @@ __device__ inline void sp_tiles(const SplitArgs& a, const SpWg& w, const double2
   for (int t = w.g; t < n_tiles; t += a.G) {
     int j, it;
     tile_coords(op.nang, op.n_itiles, t, j, it);
-    const SH<double> r = apply_tile<double, TWO, kGatherBatch, 1>(op, xin + base, j, it * kTileR, L.tl, L.tile, &L.tl2);
+    const SH<double> r = apply_tile<double, TWO, kSpGB, kSpTR>(op, xin + base, j, it * kTileR, L.tl, L.tile, &L.tl2);
     const long e = tile_elem(op.nr, j, it);
     if (e >= 0) f(base + e, r.sx, r.hx, r.hx2);
   }
@@ -175,16 +199,8 @@ __device__ inline void sp_begin_step(const SplitArgs& a, int b, SplitCtl& c, dou
 
 // ---- kernels
 
-constexpr int kSpWaves = 2;  // waves per SIMD asked of the apply and chain kernels (<= 256 registers)
-#ifndef TDDE_SPLIT_CHAIN_AHEAD
-#define TDDE_SPLIT_CHAIN_AHEAD 1
-#endif
-#ifndef TDDE_SPLIT_CHAIN_WAVES
-#define TDDE_SPLIT_CHAIN_WAVES 2
-#endif
-// rows of factor operands in flight per lane in the chain solves, and the waves per SIMD asked of them
-constexpr int kSpChainAhead = TDDE_SPLIT_CHAIN_AHEAD;
-constexpr int kSpChainWaves = TDDE_SPLIT_CHAIN_WAVES;
+
+
 
 __global__ void sp_begin_kernel(SplitArgs a) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -250,24 +266,22 @@ void sp_prologue_kernel(SplitArgs a) {
   }
 }
 
-// Chain work item of a work-group (the channel order: channels of one factor block on one XCD): its
-// channel's inputs and outputs; false for a padding item.
-__device__ inline bool sp_item(const SplitArgs& a, int b, double2* in, double2* out, double2 c1, double2 c2,
-                               ChainIO<double>& io, int& blk) {
-  const int j = a.pc.chain_order[blockIdx.x];
-  if (j < 0) return false;
-  const size_t cb = (size_t)b * a.E + (size_t)j * 2 * a.op.nr;
-  io.r = a.r + cb;
-  io.v = a.v + cb;
-  io.pz = in + cb;
-  io.out = out + cb;
+// Chain work item of a work-group (the channels of one factor block, items of a block on one XCD):
+// instance vectors and channel list; 0 channels for a padding item.
+__device__ inline int sp_item(const SplitArgs& a, int b, double2* in, double2* out, double2 c1, double2 c2,
+                              ChainIO<double>& io, const int*& js) {
+  const int nk = chain_item(a.pc, blockIdx.x, js);
+  const size_t ib = (size_t)b * a.E;
+  io.r = a.r + ib;
+  io.v = a.v + ib;
+  io.pz = in + ib;
+  io.out = out + ib;
   io.c1 = c1;
   io.c2 = c2;
-  blk = a.pc.block_of[j];
-  return true;
+  return nk;
 }
 
-// p = r (new cycle) or r + beta (p - omega v), p^ = K^-1 p: one channel per work-group.
+// p = r (new cycle) or r + beta (p - omega v), p^ = K^-1 p: one chain work item per work-group.
 __global__ __attribute__((amdgpu_flat_work_group_size(kThreads, kThreads), amdgpu_waves_per_eu(kSpChainWaves)))
 void sp_dir_chain_kernel(SplitArgs a) {
   __shared__ ChainLds<double> L;
@@ -275,10 +289,12 @@ void sp_dir_chain_kernel(SplitArgs a) {
   const SplitCtl c = a.ctl[b];
   if (c.state != SP_ACTIVE) return;
   ChainIO<double> io;
-  int blk = 0;
-  if (!sp_item(a, b, a.p, a.ph, c.beta, c.omega, io, blk)) return;
-  if (c.fresh) chain_solve<double, MODE_FRESH, kSpChainAhead>(a.pc, blk, a.op.nr, io, L);
-  else chain_solve<double, MODE_P, kSpChainAhead>(a.pc, blk, a.op.nr, io, L);
+  const int* js = nullptr;
+  const int nk = sp_item(a, b, a.p, a.ph, c.beta, c.omega, io, js);
+  if (nk == 0) return;
+  const int blk = a.pc.block_of[js[0]];
+  if (c.fresh) chain_solve<double, MODE_FRESH, kSpChainAhead>(a.pc, blk, a.op.nr, io, js, nk, L);
+  else chain_solve<double, MODE_P, kSpChainAhead>(a.pc, blk, a.op.nr, io, js, nk, L);
 }
 
 // Without the preconditioner: p = r or r + beta (p - omega v).
@@ -362,9 +378,10 @@ void sp_chain_s_kernel(SplitArgs a) {
   const SplitCtl c = a.ctl[b];
   if (c.state != SP_ACTIVE) return;
   ChainIO<double> io;
-  int blk = 0;
-  if (!sp_item(a, b, a.s, a.sh, c.alpha, c.alpha, io, blk)) return;
-  chain_solve<double, MODE_IN_S, kSpChainAhead>(a.pc, blk, a.op.nr, io, L);
+  const int* js = nullptr;
+  const int nk = sp_item(a, b, a.s, a.sh, c.alpha, c.alpha, io, js);
+  if (nk == 0) return;
+  chain_solve<double, MODE_IN_S, kSpChainAhead>(a.pc, a.pc.block_of[js[0]], a.op.nr, io, js, nk, L);
 }
 
 // t = A s^, <t, s>, <t, t> -> omega.
@@ -525,7 +542,7 @@ __global__ void sp_sync_kernel(SplitArgs a, int parity) {
 
 }  // namespace
 
-hipError_t split_launch_block(const SplitArgs& a, hipStream_t stream, int parity, bool first) {
+hipError_t split_launch_block(const SplitArgs& a, hipStream_t stream, int parity, bool first, const hipEvent_t* ev_v) {
   const dim3 blk(kThreads);
   const dim3 flat((unsigned)(a.B * a.G));
   const dim3 chains((unsigned)a.pc.n_items, (unsigned)a.B);
@@ -533,7 +550,15 @@ hipError_t split_launch_block(const SplitArgs& a, hipStream_t stream, int parity
   hipLaunchKernelGGL(sp_prologue_kernel, flat, blk, 0, stream, a);
   if (a.use_prec) hipLaunchKernelGGL(sp_dir_chain_kernel, chains, blk, 0, stream, a);
   else hipLaunchKernelGGL(sp_dir_plain_kernel, flat, blk, 0, stream, a);
+  if (ev_v != nullptr) {
+    const hipError_t e = hipEventRecord(ev_v[0], stream);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(sp_apply_v_kernel, flat, blk, 0, stream, a);
+  if (ev_v != nullptr) {
+    const hipError_t e = hipEventRecord(ev_v[1], stream);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(sp_s_kernel, flat, blk, 0, stream, a);
   if (a.use_prec) hipLaunchKernelGGL(sp_chain_s_kernel, chains, blk, 0, stream, a);
   hipLaunchKernelGGL(sp_apply_t_kernel, flat, blk, 0, stream, a);

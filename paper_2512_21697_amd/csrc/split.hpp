@@ -77,6 +77,8 @@ struct SplitArgs {
 // Launch one block (one iteration of every unfinished instance) on the stream; parity: block index
 // mod 2 (the host-flag slot its sync kernel writes). first: launch the kernel that initialises the
 // control blocks before it.
-hipError_t split_launch_block(const SplitArgs& a, hipStream_t stream, int parity, bool first);
+// ev_v: when not null, events recorded right before and after the apply kernel v = A p^.
+hipError_t split_launch_block(const SplitArgs& a, hipStream_t stream, int parity, bool first,
+                              const hipEvent_t* ev_v = nullptr);
 
 }  // namespace tdde

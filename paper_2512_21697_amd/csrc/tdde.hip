@@ -63,6 +63,7 @@ struct tdde_ctx {
     hipGraphNode_t solver = nullptr, zero_cnt = nullptr;
   } cap;
   size_t cap_lu = 0, cap_t = 0;  // allocated factor / boundary-matrix elements
+  size_t order_cap = 0;          // ints of the chain-order buffer
   // workspace
   KVec<double> v64{};
   KVec<float> v32{};
@@ -108,6 +109,8 @@ struct tdde_ctx {
   int* sp_flag = nullptr;         // pinned host memory [2]: unfinished instances after a block
   hipEvent_t sp_ev[2] = {nullptr, nullptr};
   std::vector<int> ones;          // n_steps of a single step
+  std::vector<hipEvent_t> sp_tev; // timing events of the apply kernel (tdde_debug_split_timing): pairs
+  int sp_tcap = 0, sp_tn = 0;     // pairs enabled, pairs recorded
 };
 
 // persistent kernel variants, index = 2 * mixed + preconditioned (each compiled in its own object
@@ -231,16 +234,18 @@ template <typename T>
 // two work-groups per CU: the chain solve fits 256 registers per lane without spills
 __global__ __launch_bounds__(kThreads, 2) void precond_kernel(DevPrec<T> pc, int nr, const c2_t<T>* in, c2_t<T>* out, int E) {
   __shared__ ChainLds<T> lds;
-  const int j = pc.chain_order[blockIdx.x], b = blockIdx.y;
-  if (j < 0) return;  // padding item (uniform over the work-group)
-  const size_t cb = (size_t)b * E + (size_t)j * 2 * nr;
+  const int b = blockIdx.y;
+  const int* js = nullptr;
+  const int nk = chain_item(pc, blockIdx.x, js);
+  if (nk == 0) return;  // padding item (uniform over the work-group)
+  const size_t ib = (size_t)b * E;
   ChainIO<T> io;
   io.r = nullptr;
   io.v = nullptr;
-  io.pz = const_cast<c2_t<T>*>(in) + cb;
-  io.out = out + cb;
+  io.pz = const_cast<c2_t<T>*>(in) + ib;
+  io.out = out + ib;
   io.c1 = io.c2 = make_double2(0, 0);
-  chain_solve<T, MODE_IN>(pc, pc.block_of[j], nr, io, lds);
+  chain_solve<T, MODE_IN>(pc, pc.block_of[js[0]], nr, io, js, nk, lds);
 }
 
 // ------------------------------------------------------------------------------------------ helpers
@@ -304,6 +309,7 @@ tdde_status tdde_destroy(tdde_ctx* ctx) {
   if (ctx->cap.graph) (void)hipGraphDestroy(ctx->cap.graph);
   for (hipEvent_t e : ctx->sp_ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->sp_tev) (void)hipEventDestroy(e);
   if (ctx->sp_flag) (void)hipHostFree(ctx->sp_flag);
   for (void* p : ctx->allocs) (void)hipFree(p);
   delete ctx;
@@ -648,6 +654,30 @@ tdde_status tdde_set_split(tdde_ctx* c, int32_t on) {
   return TDDE_OK;
 }
 
+tdde_status tdde_debug_split_timing(tdde_ctx* c, int32_t cap) {
+  if (!c || cap < 0 || cap > (1 << 16)) return fail(c, TDDE_ERR_ARG, "cap must be 0..65536");
+  while ((int)c->sp_tev.size() < 2 * cap) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->sp_tev.push_back(e);
+  }
+  c->sp_tcap = cap;
+  c->sp_tn = 0;
+  return TDDE_OK;
+}
+
+tdde_status tdde_debug_read_split_timing(tdde_ctx* c, float* ms, int32_t cap_host, int32_t* n) {
+  if (!c || !n || (cap_host > 0 && !ms) || cap_host < 0) return fail(c, TDDE_ERR_ARG, "bad argument");
+  const int k = std::min(c->sp_tn, cap_host);
+  for (int i = 0; i < k; ++i) {
+    HIP_TRY(c, hipEventSynchronize(c->sp_tev[2 * (size_t)i + 1]));
+    HIP_TRY(c, hipEventElapsedTime(ms + i, c->sp_tev[2 * (size_t)i], c->sp_tev[2 * (size_t)i + 1]));
+  }
+  *n = k;
+  c->sp_tn = 0;
+  return TDDE_OK;
+}
+
 tdde_status tdde_debug_set_shadow(tdde_ctx* c, const void* shadow) {
   if (!c) return fail(c, TDDE_ERR_ARG, "null context");
   c->shadow = static_cast<const double2*>(shadow);
@@ -684,12 +714,12 @@ tdde_status tdde_launch_info(tdde_ctx* c, int32_t* n_wg, int32_t* per_inst) {
   return TDDE_OK;
 }
 
-// Chain work order: channels grouped by factor block (channels of one distinct kappa share their LU
-// factors), blocks dealt to the 8 XCDs greedily by channel count, and the list of XCD x placed at
-// positions w = 8 i + x. Work-group w mod G (G a multiple of 8) runs on XCD w % 8, so the channels
-// of a block run side by side on one XCD and read its factor rows through that XCD's L2 instead of
-// from memory once per XCD. Short lists are padded with -1.
-static std::vector<int> chain_order_of(const std::vector<int>& block_of, int nblk) {
+// Chain work order: the channels of every factor block (channels of one distinct kappa share their
+// LU factors) taken nc at a time into work items, blocks dealt to the 8 XCDs greedily by item count,
+// and the list of XCD x placed at positions w = 8 i + x. Work-group w mod G (G a multiple of 8) runs on
+// XCD w % 8, so the items of a block run side by side on one XCD and read its factor rows through that
+// XCD's L2 instead of from memory once per XCD. Returns [n_items][nc] channels, -1 for none.
+static std::vector<int> chain_order_of(const std::vector<int>& block_of, int nblk, int nc) {
   constexpr int kXcd = 8;
   std::vector<std::vector<int>> members(nblk);
   for (int j = 0; j < (int)block_of.size(); ++j) members[block_of[j]].push_back(j);
@@ -697,18 +727,21 @@ static std::vector<int> chain_order_of(const std::vector<int>& block_of, int nbl
   for (int b = 0; b < nblk; ++b) blocks[b] = b;
   std::stable_sort(blocks.begin(), blocks.end(),
                    [&](int a, int b) { return members[a].size() > members[b].size(); });
-  std::vector<std::vector<int>> lists(kXcd);
+  std::vector<std::vector<std::vector<int>>> lists(kXcd);
   for (int b : blocks) {
     int best = 0;
     for (int x = 1; x < kXcd; ++x)
       if (lists[x].size() < lists[best].size()) best = x;
-    lists[best].insert(lists[best].end(), members[b].begin(), members[b].end());
+    const auto& mb = members[b];
+    for (size_t i = 0; i < mb.size(); i += nc)
+      lists[best].push_back(std::vector<int>(mb.begin() + i, mb.begin() + std::min(mb.size(), i + nc)));
   }
   size_t len = 0;
   for (auto& l : lists) len = std::max(len, l.size());
-  std::vector<int> order(len * kXcd, -1);
+  std::vector<int> order(len * kXcd * nc, -1);
   for (int x = 0; x < kXcd; ++x)
-    for (size_t i = 0; i < lists[x].size(); ++i) order[i * kXcd + x] = lists[x][i];
+    for (size_t i = 0; i < lists[x].size(); ++i)
+      for (size_t k = 0; k < lists[x][i].size(); ++k) order[(i * kXcd + x) * nc + k] = lists[x][i][k];
   return order;
 }
 
@@ -895,15 +928,26 @@ tdde_status tdde_set_dt(tdde_ctx* c, double dt) {
   if (!c->prec_alloc) {
     if ((s = upload(c, (int**)&c->pc64.block_of, c->block_of.data(), c->block_of.size())) != TDDE_OK) return s;
     c->pc32.block_of = c->pc64.block_of;
-    const std::vector<int> order = chain_order_of(c->block_of, c->nblk);
-    if ((s = upload(c, (int**)&c->pc64.chain_order, order.data(), order.size())) != TDDE_OK) return s;
+    // chain order for every channel count per work-group (nc <= 8: at most nang + 8 nblk items)
+    c->order_cap = (c->d.nang + 8 * (size_t)c->nblk) * kMaxChainNc;
+    if ((s = dev_alloc(c, (int**)&c->pc64.chain_order, c->order_cap)) != TDDE_OK) return s;
     c->pc32.chain_order = c->pc64.chain_order;
-    c->pc64.n_items = c->pc32.n_items = (int)order.size();
     c->prec_alloc = true;
   }
   c->pc64.n = c->pc32.n = n;
   c->pc64.m = c->pc32.m = m;
   c->pc64.P = c->pc32.P = P;
+  {
+    // channels per chain work-group: as many as fit 256 lanes at P segments each (a power of two, so
+    // that every channel's segment groups fit its kMaxSegGroups / nc slots)
+    int nc = 1;
+    while (nc < kMaxChainNc && 2 * nc * P <= kMaxSeg) nc *= 2;
+    const std::vector<int> order = chain_order_of(c->block_of, c->nblk, nc);
+    if (order.size() > c->order_cap) return fail(c, TDDE_ERR_HIP, "chain order larger than its buffer");
+    HIP_TRY(c, hipMemcpy((void*)c->pc64.chain_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice));
+    c->pc64.nc = c->pc32.nc = nc;
+    c->pc64.n_items = c->pc32.n_items = (int)(order.size() / nc);
+  }
   auto tof = [](const std::vector<cd>& v) {
     std::vector<float> f(2 * v.size());
     for (size_t i = 0; i < v.size(); ++i) { f[2 * i] = (float)v[i].real(); f[2 * i + 1] = (float)v[i].imag(); }
@@ -1311,7 +1355,9 @@ static tdde_status run_split(tdde_ctx* c, const SolveArgs& a) {
   // least one block
   const long max_blocks = (long)a.n_chunk * ((long)a.max_iter + 24) + 4;
   for (long m = 0;; ++m) {
-    HIP_TRY(c, split_launch_block(s, c->stream, (int)(m & 1), m == 0));
+    const hipEvent_t* ev = nullptr;
+    if (c->sp_tn < c->sp_tcap) ev = &c->sp_tev[2 * (size_t)c->sp_tn++];
+    HIP_TRY(c, split_launch_block(s, c->stream, (int)(m & 1), m == 0, ev));
     HIP_TRY(c, hipEventRecord(c->sp_ev[m & 1], c->stream));
     if (m == 0) continue;
     HIP_TRY(c, hipEventSynchronize(c->sp_ev[(m - 1) & 1]));

@@ -77,3 +77,24 @@ def test_segment_length_tuning_refactors_and_keeps_fastest():
     best, times = tune_segment(s, 1e-3, s.run, candidates=(16, 24, 32, 48), reps=2, sync=lambda: None, prefer=24)
     assert best == 32 and s.seg == 32 and s.dt == 1e-3
     assert set(times) == {24, 32, 48}
+
+
+class _FormSolver:
+    def __init__(self, cost):
+        self.cost, self.split = cost, False
+
+    def set_split(self, on):
+        self.split = bool(on)
+
+    def run(self):
+        time.sleep(self.cost["split" if self.split else "persistent"])
+
+
+def test_form_picks_faster_and_prefers_within_margin():
+    from paper_2512_21697_amd.autotune import tune_form
+    s = _FormSolver({"persistent": 0.010, "split": 0.004})
+    best, times = tune_form(s, s.run, reps=2, sync=lambda: None)
+    assert best == "split" and s.split and times["split"] < times["persistent"]
+    s = _FormSolver({"persistent": 0.0100, "split": 0.0099})
+    best, _ = tune_form(s, s.run, reps=2, sync=lambda: None, prefer="persistent", margin=0.2)
+    assert best == "persistent" and not s.split
