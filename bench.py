@@ -134,7 +134,7 @@ def measured_traffic(name, launch_key, kernel="persistent_kernel"):
 # ------------------------------------------------------------------------------ GPU runs
 
 def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precision=0, launch=0, info=None,
-                  segment=None, form=None):
+                  segment=None, form=None, prec_bits=64):
     """Run warmup + timed steps of one instance in chunks of steps (one library call each).
 
     launch: work-groups per CU of the persistent grid (1..4, 0 = library default), or "auto" to
@@ -142,7 +142,8 @@ def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precisio
     under every shape and keep the fastest. segment: least rows per preconditioner segment (None =
     library default), or "auto" to tune it the same way (preconditioned runs only). form: solver form,
     "persistent" (None: the library default), "split" (one kernel per window of the iteration; FP64
-    previous-state-guess steps only) or "auto" to time both on the tuning chunk. ``info`` (a dict)
+    previous-state-guess steps only) or "auto" to time both on the tuning chunk. prec_bits: storage
+    of the preconditioner factors read by the kernel-per-window form (64, or 32). ``info`` (a dict)
     receives the choices, the timings, the grid actually launched and, in the split form, the
     durations of the timed region's apply kernel v = A p^ (HIP events on the library's stream).
     Returns (ms_per_step, stats array, [(kernel ms, steps) per launch], wall seconds, final state)."""
@@ -153,6 +154,7 @@ def run_gpu_steps(P, torch, w, steps, warmup, precond, guess, chunk=64, precisio
             s.set_prec_segment(int(segment))
         s.set_dt(w.dt)
         s.set_pulses(w.pulses)
+        s.set_prec_storage(prec_bits)
         opts = P.solve_opts(tol=1e-12, max_iter=300, guess=guess, precond=precond, precision=precision,
                             inner_tol=1e-5, max_outer=20)
         psi = torch.from_numpy(w.psi0.reshape(-1)).to("cuda:0")
@@ -679,6 +681,19 @@ def main():
         "roofline": roof,
     }
     sub = {}
+    if not args.no_headline and split_form:
+        _log("bench: beyond-dipole, FP32 preconditioner factors (same form, launch and segment)")
+        info32 = {}
+        f32_form = tuning.get("form")
+        ms32, st32, _, _, psi32 = run_gpu_steps(P, torch, w3, args.steps, args.warmup, precond=1, guess=P.GUESS_PREV,
+                                                launch=int(tuning.get("wg_per_cu", 0)), info=info32,
+                                                segment=tuning.get("segment_rows"), form=f32_form, prec_bits=32)
+        del psi32
+        sub["beyond_dipole_fp32_factors"] = {
+            "steps_per_s": 1000.0 / ms32, "ms_per_step": ms32, "iters_per_step": float(st32["iters"].mean()),
+            "all_converged": bool(np.all(st32["status"] == 0)), "max_true_rel_res": float(st32["true_rel_res"].max()),
+            "note": "preconditioner factors stored in FP32 (tdde_set_prec_storage(32)); iteration, residuals and "
+                    "states FP64 to the same 1e-12 tolerance", "launch": info32}
     if "c3plain" in sections:
         _log("bench: beyond-dipole without preconditioner")
         sub["beyond_dipole_plain"] = step_section(P, torch, w3, args.steps, args.warmup, 0, label="c3 driven, no M")

@@ -297,6 +297,14 @@ tdde_status tdde_set_prec_segment(tdde_ctx* ctx, int32_t min_rows);
  * TDDE_ERR_ARG for on outside {0, 1}. */
 tdde_status tdde_set_split(tdde_ctx* ctx, int32_t on);
 
+/* Storage precision of the preconditioner's factors (eq. matrixM: the LU of M = S + i dt/2 H0 and its
+ * segment coupling matrices) read by the kernel-per-window solver: 64 (default) or 32 bits. With 32
+ * the factors are the FP64 factorisation rounded to FP32 (the copy the mixed-precision solver uses);
+ * substitutions, vectors and every residual stay FP64, and convergence is still decided by the FP64
+ * true residual, so only the preconditioner (already an approximation of A: it omits the coupling)
+ * changes, by ~1e-7 relative. TDDE_ERR_ARG for other values. */
+tdde_status tdde_set_prec_storage(tdde_ctx* ctx, int32_t bits);
+
 /* Persistent-grid size actually used (work-groups) and the per-instance work-group count. */
 tdde_status tdde_launch_info(tdde_ctx* ctx, int32_t* n_wg, int32_t* wg_per_instance);
 

@@ -60,7 +60,7 @@ STATS_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("matvecs", "<i4"),
 EXPORTS = ["tdde_create", "tdde_assemble", "tdde_set_dt", "tdde_set_pulses", "tdde_set_field_table", "tdde_eval_pulses", "tdde_set_field", "tdde_apply",
            "tdde_apply_c64", "tdde_precond_apply", "tdde_solve", "tdde_solve_static", "tdde_step", "tdde_spectrum_setup", "tdde_spectrum",
            "tdde_spectrum_error", "tdde_run_batched", "tdde_destroy",
-           "tdde_launch_info", "tdde_set_launch", "tdde_set_prec_segment", "tdde_set_split", "tdde_set_graph", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
+           "tdde_launch_info", "tdde_set_launch", "tdde_set_prec_segment", "tdde_set_split", "tdde_set_prec_storage", "tdde_set_graph", "tdde_status_string", "tdde_last_error", "tdde_debug_phase_marks",
            "tdde_debug_read_marks", "tdde_debug_set_shadow", "tdde_debug_split_timing", "tdde_debug_read_split_timing", "tdde_mlp_create", "tdde_mlp_destroy",
            "tdde_mlp_param_count", "tdde_mlp_set_params", "tdde_mlp_get_params", "tdde_mlp_get_grads",
            "tdde_mlp_forward", "tdde_mlp_backward", "tdde_mlp_adam", "tdde_mlp_set_pulses", "tdde_mlp_guess",
@@ -101,6 +101,7 @@ def load():
         "tdde_set_launch": [P, C.c_int32],
         "tdde_set_prec_segment": [P, C.c_int32],
         "tdde_set_split": [P, C.c_int32],
+        "tdde_set_prec_storage": [P, C.c_int32],
         "tdde_set_graph": [P, C.c_int32],
         "tdde_debug_phase_marks": [P, C.c_int32],
         "tdde_debug_read_marks": [P, P, C.c_int32],
@@ -407,6 +408,10 @@ class Solver:
         """Kernel-per-window solver for FP64 steps with the previous-state guess (True), or one
         persistent launch per call (False, the default)."""
         self._check(self.lib.tdde_set_split(self.h, 1 if on else 0))
+
+    def set_prec_storage(self, bits: int):
+        """Preconditioner factors read by the kernel-per-window solver in 64 (default) or 32 bits."""
+        self._check(self.lib.tdde_set_prec_storage(self.h, int(bits)))
 
     def split_timing(self, cap: int):
         """Record the launch durations of the kernel-per-window form's apply kernel v = A p^ for the

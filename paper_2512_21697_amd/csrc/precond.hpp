@@ -105,6 +105,10 @@ constexpr int kChainAhead = TDDE_CHAIN_AHEAD;
 // Substitution kinds: lower phase 1 (forms the input), lower phase 3, upper phase 1, upper phase 3.
 enum { SUB_L1 = 0, SUB_L3 = 1, SUB_U1 = 2, SUB_U3 = 3 };
 
+// Complex value of another precision (the factors may be stored in FP32 for an FP64 solve).
+template <typename T> __device__ inline c2_t<T> cvt(double2 z) { return cmk<T>((T)z.x, (T)z.y); }
+template <typename T> __device__ inline c2_t<T> cvt(float2 z) { return cmk<T>((T)z.x, (T)z.y); }
+
 // Factor entries of one row: L row: W values; U row: 1/U(q,q) and W values.
 template <typename T, int NC> struct RowOps {
   c2_t<T> c[NC];
@@ -165,8 +169,8 @@ __device__ inline c2_t<T> stage_input(const ChainIO<T>& io, long e) {
 // wave's loads are runs of whole pieces instead of one element per segment m / 2 elements apart),
 // every lane substitutes its rows from LDS, and phase-3 kinds write their results back through LDS
 // the same way. Phase-1 kinds keep only the window. All threads call (barriers inside).
-template <typename T, int KIND, int MODE, int W, int D = kChainAhead>
-__device__ inline void substitute(const c2_t<T>* LU, int P, int m, int n, int nk, const ChainIO<T>& io, int nr,
+template <typename T, int KIND, int MODE, int W, int D = kChainAhead, typename TF = T>
+__device__ inline void substitute(const c2_t<TF>* LU, int P, int m, int n, int nk, const ChainIO<T>& io, int nr,
                                   int len, c2_t<T> (&win)[W], ChainLds<T>& L) {
   constexpr bool lower = KIND <= SUB_L3;
   constexpr bool writes = KIND == SUB_L3 || KIND == SUB_U3;
@@ -175,10 +179,10 @@ __device__ inline void substitute(const c2_t<T>* LU, int P, int m, int n, int nk
   static_assert(C % D == 0, "the steps of a chunk must be whole rounds of the lookahead");
   const int lane = threadIdx.x;
   const int nl = nk * P;  // lanes with a segment
-  RowOps<T, NC> ro[D];
+  RowOps<TF, NC> ro[D];
 #pragma unroll
   for (int d = 0; d < D; ++d)
-    if (d < len) row_fetch<T, KIND, NC>(ro[d], LU, lower ? d : len - 1 - d, P);
+    if (d < len) row_fetch<TF, KIND, NC>(ro[d], LU, lower ? d : len - 1 - d, P);
   auto elem = [&](int idx, int c0, int& uu) {
     const int ln = idx / C;
     uu = idx - ln * C;
@@ -201,12 +205,12 @@ __device__ inline void substitute(const c2_t<T>* LU, int P, int m, int n, int nk
         if (u < len) {
           c2_t<T> acc = L.stage[uu][lane];
 #pragma unroll
-          for (int k = 0; k < W; ++k) acc = cfms<T>(ro[d].c[lower ? k : k + 1], win[k], acc);
-          if (!lower) acc = cmul<T>(acc, ro[d].c[0]);
+          for (int k = 0; k < W; ++k) acc = cfms<T>(cvt<T>(ro[d].c[lower ? k : k + 1]), win[k], acc);
+          if (!lower) acc = cmul<T>(acc, cvt<T>(ro[d].c[0]));
 #pragma unroll
           for (int k = W - 1; k > 0; --k) win[k] = win[k - 1];
           win[0] = acc;
-          if (u + D < len) row_fetch<T, KIND, NC>(ro[d], LU, lower ? u + D : len - 1 - u - D, P);
+          if (u + D < len) row_fetch<TF, KIND, NC>(ro[d], LU, lower ? u + D : len - 1 - u - D, P);
           if (writes) L.stage[uu][lane] = acc;
         }
       }
@@ -236,8 +240,8 @@ __device__ inline void wave_sync() {
 // slot 4v + k. The T row of the next step is loaded one step ahead.
 //   lower: t_p = g_p - T_p t_{p-1}, p ascending from the group's first segment;
 //   upper: h_p = g_p - T_p h_{p+1}, p descending from the group's last segment.
-template <typename T, bool LOWER, int W>
-__device__ inline void group_recurrence(const c2_t<T>* Tm, int P, int nc, int nk, ChainLds<T>& L) {
+template <typename T, bool LOWER, int W, typename TF = T>
+__device__ inline void group_recurrence(const c2_t<TF>* Tm, int P, int nc, int nk, ChainLds<T>& L) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int k = lane / W, r = lane - k * W;
   const int slot = wave * 4 + k, GS = kMaxSegGroups / nc;
@@ -245,7 +249,7 @@ __device__ inline void group_recurrence(const c2_t<T>* Tm, int P, int nc, int nk
   const int lo = g * kSegGroup, hi = min(lo + kSegGroup - 1, P - 1);
   const bool act = lane < 4 * W && kk < nk && lo < P;
   const int base = kk * P;  // lane of the channel's segment 0
-  c2_t<T> tr[W];
+  c2_t<TF> tr[W];
   auto fetch = [&](int step) {
     const int p = LOWER ? lo + step : hi - step;
     if (act && step < kSegGroup && (LOWER ? p <= hi : p >= lo)) {
@@ -262,7 +266,7 @@ __device__ inline void group_recurrence(const c2_t<T>* Tm, int P, int nc, int nk
       const int prev = LOWER ? p - 1 : p + 1;
       acc = L.win[base + p][r];
 #pragma unroll
-      for (int c = 0; c < W; ++c) acc = cfms<T>(tr[c], L.win[base + prev][c], acc);
+      for (int c = 0; c < W; ++c) acc = cfms<T>(cvt<T>(tr[c]), L.win[base + prev][c], acc);
     }
     fetch(step + 1);
     wave_sync();
@@ -275,8 +279,8 @@ __device__ inline void group_recurrence(const c2_t<T>* Tm, int P, int nc, int nk
 // boundary of every group of the channel, in order,
 //   lower: u_0 = t_hi(0), u_G = t^loc_hi(G) + CL_hi(G) u_{G-1};
 //   upper: u_last = h_lo(last), u_G = h^loc_lo(G) + CU_lo(G) u_{G+1}.
-template <typename T, bool LOWER, int W>
-__device__ inline void group_boundaries(const c2_t<T>* Cm, int P, int nc, int nk, ChainLds<T>& L) {
+template <typename T, bool LOWER, int W, typename TF = T>
+__device__ inline void group_boundaries(const c2_t<TF>* Cm, int P, int nc, int nk, ChainLds<T>& L) {
   const int kk = threadIdx.x >> 4, r = threadIdx.x & 15;
   if (kk >= nk || r >= W) return;
   const int NG = (P + kSegGroup - 1) / kSegGroup;
@@ -285,7 +289,7 @@ __device__ inline void group_boundaries(const c2_t<T>* Cm, int P, int nc, int nk
   auto seg_of = [&](int G) { return LOWER ? min(G * kSegGroup + kSegGroup - 1, P - 1) : G * kSegGroup; };
   const int G0 = LOWER ? 0 : NG - 1;
   L.u[us + G0][r] = L.win[base + seg_of(G0)][r];
-  c2_t<T> cr[W];
+  c2_t<TF> cr[W];
   auto fetch = [&](int G) {
     if (G >= 0 && G < NG && G != G0) {
       const int p = seg_of(G);
@@ -300,7 +304,7 @@ __device__ inline void group_boundaries(const c2_t<T>* Cm, int P, int nc, int nk
     wave_sync();
     c2_t<T> acc = L.win[base + seg_of(G)][r];
 #pragma unroll
-    for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(cr[c], L.u[us + Gin][c]));
+    for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(cvt<T>(cr[c]), L.u[us + Gin][c]));
     fetch(LOWER ? G + 1 : G - 1);
     wave_sync();
     L.u[us + G][r] = acc;
@@ -310,8 +314,8 @@ __device__ inline void group_boundaries(const c2_t<T>* Cm, int P, int nc, int nk
 // True boundary window of segment q of channel kk into out[W]: the group-local window corrected by
 // the group product times the true boundary entering the group (nothing to correct in the group where
 // the recurrence starts).
-template <typename T, bool LOWER, int W>
-__device__ inline void true_window(const c2_t<T>* Cm, int P, int nc, int kk, int q, const ChainLds<T>& L,
+template <typename T, bool LOWER, int W, typename TF = T>
+__device__ inline void true_window(const c2_t<TF>* Cm, int P, int nc, int kk, int q, const ChainLds<T>& L,
                                    c2_t<T> (&out)[W]) {
   const int NG = (P + kSegGroup - 1) / kSegGroup;
   const int G = q / kSegGroup;
@@ -327,7 +331,7 @@ __device__ inline void true_window(const c2_t<T>* Cm, int P, int nc, int kk, int
     for (int rr = 0; rr < W; ++rr) {
       c2_t<T> acc = out[rr];
 #pragma unroll
-      for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(gld(Cm + ((size_t)rr * W + c) * P + q), uu[c]));
+      for (int c = 0; c < W; ++c) acc = cadd<T>(acc, cmul<T>(cvt<T>(gld(Cm + ((size_t)rr * W + c) * P + q)), uu[c]));
       out[rr] = acc;
     }
   }
@@ -336,20 +340,20 @@ __device__ inline void true_window(const c2_t<T>* Cm, int P, int nc, int kk, int
 // Solve M_blk z = input for the channels js[0 .. nk) (nk <= pc.nc) of factor block blk with the whole
 // work-group (all threads call it). io holds the instance's vectors; D: rows of factor operands a lane
 // keeps in flight in the substitutions.
-template <typename T, int MODE, int D = kChainAhead>
-__device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int blk, int nr, const ChainIO<T>& io,
+template <typename T, int MODE, int D = kChainAhead, typename TF = T>
+__device__ __attribute__((noinline)) void chain_solve(const DevPrec<TF>& pc, int blk, int nr, const ChainIO<T>& io,
                                                       const int* js, int nk, ChainLds<T>& L) {
   constexpr int W = kPrecW;
   const int t = threadIdx.x;
   const int P = pc.P, m = pc.m, n = pc.n, nc = pc.nc;
   const int kk = t / P, p = t - kk * P;  // channel slot and segment of this lane
   const bool on = kk < nk;
-  const c2_t<T>* LU = pc.LU + (size_t)blk * m * kPrecStride * P + (on ? p : 0);
+  const c2_t<TF>* LU = pc.LU + (size_t)blk * m * kPrecStride * P + (on ? p : 0);
   const size_t tsz = (size_t)P * W * W;
-  const c2_t<T>* TL = pc.TL + blk * tsz;
-  const c2_t<T>* TU = pc.TU + blk * tsz;
-  const c2_t<T>* CL = pc.CL + blk * tsz;
-  const c2_t<T>* CU = pc.CU + blk * tsz;
+  const c2_t<TF>* TL = pc.TL + blk * tsz;
+  const c2_t<TF>* TU = pc.TU + blk * tsz;
+  const c2_t<TF>* CL = pc.CL + blk * tsz;
+  const c2_t<TF>* CU = pc.CU + blk * tsz;
   const int len = on ? min(m, n - p * m) : 0;
   c2_t<T> win[W], tw[W];
   __syncthreads();  // a previous solve of this work-group has finished with coff
@@ -358,7 +362,7 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int 
   // ---- lower solve, phase 1: local windows; tail t_p[c] = y[o + len - W + c] = win[W-1-c]
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_L1, MODE, W, D>(LU, P, m, n, nk, io, nr, len, win, L);
+  substitute<T, SUB_L1, MODE, W, D, TF>(LU, P, m, n, nk, io, nr, len, win, L);
   __syncthreads();  // every lane is done with the staged steps
   if (on) {
 #pragma unroll
@@ -366,45 +370,45 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<T>& pc, int 
   }
   __syncthreads();
   // ---- phase 2: group recurrences, group boundaries
-  group_recurrence<T, true, W>(TL, P, nc, nk, L);
+  group_recurrence<T, true, W, TF>(TL, P, nc, nk, L);
   __syncthreads();
-  group_boundaries<T, true, W>(CL, P, nc, nk, L);
+  group_boundaries<T, true, W, TF>(CL, P, nc, nk, L);
   __syncthreads();
   // ---- phase 3: final substitution from the true window win[k] = y_{o-1-k} = t_{p-1}[W-1-k]
   if (on && p > 0) {
-    true_window<T, true, W>(CL, P, nc, kk, p - 1, L, tw);
+    true_window<T, true, W, TF>(CL, P, nc, kk, p - 1, L, tw);
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = tw[W - 1 - k];
   } else {
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_L3, MODE, W, D>(LU, P, m, n, nk, io, nr, len, win, L);
+  substitute<T, SUB_L3, MODE, W, D, TF>(LU, P, m, n, nk, io, nr, len, win, L);
 
   // ---- upper solve, phase 1: heads h_p[c] = x[o + c] = win[c] with zero incoming window
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_U1, MODE, W, D>(LU, P, m, n, nk, io, nr, len, win, L);
+  substitute<T, SUB_U1, MODE, W, D, TF>(LU, P, m, n, nk, io, nr, len, win, L);
   __syncthreads();  // every thread has read its lower window
   if (on) {
 #pragma unroll
     for (int c = 0; c < W; ++c) L.win[t][c] = win[c];
   }
   __syncthreads();
-  group_recurrence<T, false, W>(TU, P, nc, nk, L);
+  group_recurrence<T, false, W, TF>(TU, P, nc, nk, L);
   __syncthreads();
-  group_boundaries<T, false, W>(CU, P, nc, nk, L);
+  group_boundaries<T, false, W, TF>(CU, P, nc, nk, L);
   __syncthreads();
   // ---- phase 3: x from the true incoming window win[k] = x_{o+len+k} = h_{p+1}[k]
   if (on && p + 1 < P) {
-    true_window<T, false, W>(CU, P, nc, kk, p + 1, L, tw);
+    true_window<T, false, W, TF>(CU, P, nc, kk, p + 1, L, tw);
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = tw[k];
   } else {
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_U3, MODE, W, D>(LU, P, m, n, nk, io, nr, len, win, L);
+  substitute<T, SUB_U3, MODE, W, D, TF>(LU, P, m, n, nk, io, nr, len, win, L);
 }
 
 }  // namespace tdde

@@ -27,8 +27,13 @@ constexpr int kSpTR = TDDE_SPLIT_TR;
 #ifndef TDDE_SPLIT_CHAIN_WAVES
 #define TDDE_SPLIT_CHAIN_WAVES 2
 #endif
-// rows of factor operands in flight per lane in the chain solves, and the waves per SIMD asked of them
+#ifndef TDDE_SPLIT_CHAIN_AHEAD32
+#define TDDE_SPLIT_CHAIN_AHEAD32 1
+#endif
+// rows of factor operands in flight per lane in the chain solves (FP64 factors; FP32 factors take half
+// the registers per row), and the waves per SIMD asked of them
 constexpr int kSpChainAhead = TDDE_SPLIT_CHAIN_AHEAD;
+constexpr int kSpChainAhead32 = TDDE_SPLIT_CHAIN_AHEAD32;
 constexpr int kSpChainWaves = TDDE_SPLIT_CHAIN_WAVES;
 
 // Work-group -> (instance b, work-group g of the instance) for the apply and vector kernels of a
@@ -293,8 +298,13 @@ void sp_dir_chain_kernel(SplitArgs a) {
   const int nk = sp_item(a, b, a.p, a.ph, c.beta, c.omega, io, js);
   if (nk == 0) return;
   const int blk = a.pc.block_of[js[0]];
-  if (c.fresh) chain_solve<double, MODE_FRESH, kSpChainAhead>(a.pc, blk, a.op.nr, io, js, nk, L);
-  else chain_solve<double, MODE_P, kSpChainAhead>(a.pc, blk, a.op.nr, io, js, nk, L);
+  if (a.prec32) {
+    if (c.fresh) chain_solve<double, MODE_FRESH, kSpChainAhead32, float>(a.pc32, blk, a.op.nr, io, js, nk, L);
+    else chain_solve<double, MODE_P, kSpChainAhead32, float>(a.pc32, blk, a.op.nr, io, js, nk, L);
+  } else {
+    if (c.fresh) chain_solve<double, MODE_FRESH, kSpChainAhead>(a.pc, blk, a.op.nr, io, js, nk, L);
+    else chain_solve<double, MODE_P, kSpChainAhead>(a.pc, blk, a.op.nr, io, js, nk, L);
+  }
 }
 
 // Without the preconditioner: p = r or r + beta (p - omega v).
@@ -381,7 +391,8 @@ void sp_chain_s_kernel(SplitArgs a) {
   const int* js = nullptr;
   const int nk = sp_item(a, b, a.s, a.sh, c.alpha, c.alpha, io, js);
   if (nk == 0) return;
-  chain_solve<double, MODE_IN_S, kSpChainAhead>(a.pc, a.pc.block_of[js[0]], a.op.nr, io, js, nk, L);
+  if (a.prec32) chain_solve<double, MODE_IN_S, kSpChainAhead32, float>(a.pc32, a.pc.block_of[js[0]], a.op.nr, io, js, nk, L);
+  else chain_solve<double, MODE_IN_S, kSpChainAhead>(a.pc, a.pc.block_of[js[0]], a.op.nr, io, js, nk, L);
 }
 
 // t = A s^, <t, s>, <t, t> -> omega.

@@ -58,6 +58,7 @@ constexpr int kSpCntLine = 64;  // ints per arrival counter (one 256-byte line p
 struct SplitArgs {
   DevOp<double> op;
   DevPrec<double> pc;
+  DevPrec<float> pc32;     // the same factors rounded to FP32 (used when prec32 is set)
   double2 *x, *r, *rh, *p, *ph, *v, *s, *sh, *t;  // ph == p, sh == s without the preconditioner
   double2* bvec[2];        // right-hand sides of this step and the next
   double2* part;           // [B][G][kSpSlots]
@@ -70,7 +71,7 @@ struct SplitArgs {
   int* host_flag;          // host-visible [2]: unfinished instances after a block, by block parity
   int ftab_rows, n_fields;
   int B, E, G;             // G: work-groups per instance of the apply and vector kernels (multiple of 8)
-  int step0, n_chunk, max_iter, use_prec, pad;
+  int step0, n_chunk, max_iter, use_prec, prec32;
   double tol, dt, t0;
 };
 

@@ -102,6 +102,7 @@ struct tdde_ctx {
   double* spec_err = nullptr;     // [batch]
   // kernel-per-window solver (tdde_set_split)
   bool split = false;
+  bool prec_f32 = false;          // FP32 preconditioner factors in the kernel-per-window solver
   int sp_G = 0;                   // work-groups per instance of its apply and vector kernels
   SplitCtl* sp_ctl = nullptr;     // [batch] control blocks
   int* sp_cnt = nullptr;          // [batch][kSpCntLine] arrival counters
@@ -651,6 +652,13 @@ tdde_status tdde_set_split(tdde_ctx* c, int32_t on) {
     c->sp_G = G;
   }
   c->split = on != 0;
+  return TDDE_OK;
+}
+
+tdde_status tdde_set_prec_storage(tdde_ctx* c, int32_t bits) {
+  if (!c) return fail(c, TDDE_ERR_ARG, "null context");
+  if (bits != 32 && bits != 64) return fail(c, TDDE_ERR_ARG, "bits must be 32 or 64");
+  c->prec_f32 = bits == 32;
   return TDDE_OK;
 }
 
@@ -1319,6 +1327,8 @@ static tdde_status run_split(tdde_ctx* c, const SolveArgs& a) {
   SplitArgs s{};
   s.op = c->op64;
   s.pc = c->pc64;
+  s.pc32 = c->pc32;
+  s.prec32 = c->prec_f32 ? 1 : 0;
   const KVec<double>& V = a.v64;
   s.x = a.psi;
   s.r = V.r;
