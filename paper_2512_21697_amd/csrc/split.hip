@@ -128,6 +128,26 @@ __device__ inline void sp_elems(const SplitArgs& a, const SpWg& w, F&& f) {
   for (size_t e = (size_t)w.g * kThreads + threadIdx.x; e < (size_t)a.E; e += stride) f(base + e);
 }
 
+// The same elements in batches of VB per thread: load(e) for the VB elements of a batch, then
+// compute(e, loaded) in element order (per-thread order as in sp_elems), so that a thread has the
+// loads of VB elements in flight at once (VB sized so that four waves per SIMD stay resident: the
+// grid holds four work-groups per CU).
+template <int kVB, typename LD, typename CP>
+__device__ inline void sp_elems_batched(const SplitArgs& a, const SpWg& w, LD&& load, CP&& compute) {
+  const size_t base = (size_t)w.b * a.E;
+  const size_t stride = (size_t)a.G * kThreads;
+  size_t e = (size_t)w.g * kThreads + threadIdx.x;
+  using V = decltype(load(size_t(0)));
+  for (; e + (kVB - 1) * stride < (size_t)a.E; e += kVB * stride) {
+    V v[kVB];
+#pragma unroll
+    for (int u = 0; u < kVB; ++u) v[u] = load(base + e + u * stride);
+#pragma unroll
+    for (int u = 0; u < kVB; ++u) compute(base + e + u * stride, v[u]);
+  }
+  for (; e < (size_t)a.E; e += stride) compute(base + e, load(base + e));
+}
+
 __device__ inline bool sp_next_exists(const SplitArgs& a, int b, const SplitCtl& c) {
   return c.k + 1 < a.n_chunk && c.step + 1 < a.n_steps[b];
 }
@@ -363,11 +383,14 @@ __global__ __launch_bounds__(kThreads) void sp_s_kernel(SplitArgs a) {
   if (c.state != SP_ACTIVE) return;
   const double2 al = c.alpha;
   double n2 = 0.0;
-  sp_elems(a, w, [&](size_t e) {
-    const double2 sv = csub<double>(a.r[e], cmul<double>(al, a.v[e]));
-    a.s[e] = sv;
-    n2 += sv.x * sv.x + sv.y * sv.y;
-  });
+  struct RV { double2 r, v; };
+  sp_elems_batched<4>(
+      a, w, [&](size_t e) { return RV{gld(a.r + e), gld(a.v + e)}; },
+      [&](size_t e, RV q) {
+        const double2 sv = csub<double>(q.r, cmul<double>(al, q.v));
+        gst(a.s + e, sv);
+        n2 += sv.x * sv.x + sv.y * sv.y;
+      });
   sp_partial(a, w, SPS_A, make_double2(n2, 0.0), R);
   if (!sp_last(a, w, R)) return;
   const double ss = sp_total(a, w.b, SPS_A, R).x;
@@ -435,19 +458,26 @@ __global__ __launch_bounds__(kThreads) void sp_xr_kernel(SplitArgs a) {
   const SplitCtl c = a.ctl[w.b];
   const double2 al = c.alpha;
   if (c.state == SP_HALF) {
-    sp_elems(a, w, [&](size_t e) { a.x[e] = cfma<double>(al, a.ph[e], a.x[e]); });
+    struct XP { double2 x, ph; };
+    sp_elems_batched<4>(
+        a, w, [&](size_t e) { return XP{gld(a.x + e), gld(a.ph + e)}; },
+        [&](size_t e, XP q) { gst(a.x + e, cfma<double>(al, q.ph, q.x)); });
     return;
   }
   if (c.state != SP_ACTIVE) return;
   const double2 om = c.omega;
   double2 rho = make_double2(0.0, 0.0), rr = rho;
-  sp_elems(a, w, [&](size_t e) {
-    a.x[e] = cfma<double>(om, a.sh[e], cfma<double>(al, a.ph[e], a.x[e]));
-    const double2 rv = csub<double>(a.s[e], cmul<double>(om, a.t[e]));
-    a.r[e] = rv;
-    dot_acc(rho, a.rh[e], rv);
-    dot_acc(rr, rv, rv);
-  });
+  struct XR { double2 x, ph, sh, s, t, rh; };
+  sp_elems_batched<2>(
+      a, w,
+      [&](size_t e) { return XR{gld(a.x + e), gld(a.ph + e), gld(a.sh + e), gld(a.s + e), gld(a.t + e), gld(a.rh + e)}; },
+      [&](size_t e, XR q) {
+        gst(a.x + e, cfma<double>(om, q.sh, cfma<double>(al, q.ph, q.x)));
+        const double2 rv = csub<double>(q.s, cmul<double>(om, q.t));
+        gst(a.r + e, rv);
+        dot_acc(rho, q.rh, rv);
+        dot_acc(rr, rv, rv);
+      });
   sp_partial(a, w, SPS_A, rho, R);
   sp_partial(a, w, SPS_B, rr, R);
   if (!sp_last(a, w, R)) return;
