@@ -16,9 +16,10 @@
 //      corrected by C_p times the true boundary entering its group;
 //   3. every thread substitutes through its segment again from its true boundary window.
 // A work-group solves nc channels of one factor block at once (nc = 256 / P rounded down to a power of
-// two, at most 8): lane t = kk P + p runs segment p of channel kk, so the lanes of the nc channels read
-// the same factor rows, and phase 2 runs for all channels side by side (kSegGroup-segment groups of
-// every channel in their own slots).
+// two, at most 8): lane t = p nc + kk runs segment p of channel kk, so the nc lanes that read the same
+// factor rows sit side by side in one wave and every factor load of a wave touches the rows of 64 / nc
+// segments once; phase 2 runs for all channels side by side (kSegGroup-segment groups of every
+// channel in their own slots; boundary windows in LDS by channel, win[kk P + p]).
 // Factor storage per block, row q = p m + t of segment p: entry k of the row is LU[t][k][p] (the
 // segment index fastest, so the threads of a wave read consecutive addresses), with entries
 // 0..w-1 = L(q, q-1-k), w = 1 / U(q, q), w+1+k = U(q, q+1+k); TL, TU [p][c][r] = T_p(r, c);
@@ -170,7 +171,7 @@ __device__ inline c2_t<T> stage_input(const ChainIO<T>& io, long e) {
 // every lane substitutes its rows from LDS, and phase-3 kinds write their results back through LDS
 // the same way. Phase-1 kinds keep only the window. All threads call (barriers inside).
 template <typename T, int KIND, int MODE, int W, int D = kChainAhead, typename TF = T>
-__device__ inline void substitute(const c2_t<TF>* LU, int P, int m, int n, int nk, const ChainIO<T>& io, int nr,
+__device__ inline void substitute(const c2_t<TF>* LU, int P, int m, int n, int nc, int nk, const ChainIO<T>& io, int nr,
                                   int len, c2_t<T> (&win)[W], ChainLds<T>& L) {
   constexpr bool lower = KIND <= SUB_L3;
   constexpr bool writes = KIND == SUB_L3 || KIND == SUB_U3;
@@ -178,7 +179,7 @@ __device__ inline void substitute(const c2_t<TF>* LU, int P, int m, int n, int n
   constexpr int C = kStageRows;
   static_assert(C % D == 0, "the steps of a chunk must be whole rounds of the lookahead");
   const int lane = threadIdx.x;
-  const int nl = nk * P;  // lanes with a segment
+  const int nl = nc * P;  // lanes that may hold a segment (those of channel slots kk >= nk hold none)
   RowOps<TF, NC> ro[D];
 #pragma unroll
   for (int d = 0; d < D; ++d)
@@ -186,8 +187,9 @@ __device__ inline void substitute(const c2_t<TF>* LU, int P, int m, int n, int n
   auto elem = [&](int idx, int c0, int& uu) {
     const int ln = idx / C;
     uu = idx - ln * C;
-    const int kk = ln / P;
-    const long e = step_elem(ln - kk * P, c0 + uu, m, n, nr, lower);
+    const int kk = ln % nc;
+    if (kk >= nk) return -1L;
+    const long e = step_elem(ln / nc, c0 + uu, m, n, nr, lower);
     return e >= 0 ? L.coff[kk] + e : -1L;
   };
   for (int c0 = 0; c0 < m; c0 += C) {
@@ -346,8 +348,8 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<TF>& pc, int
   constexpr int W = kPrecW;
   const int t = threadIdx.x;
   const int P = pc.P, m = pc.m, n = pc.n, nc = pc.nc;
-  const int kk = t / P, p = t - kk * P;  // channel slot and segment of this lane
-  const bool on = kk < nk;
+  const int kk = t % nc, p = t / nc;  // channel slot and segment of this lane
+  const bool on = kk < nk && p < P;
   const c2_t<TF>* LU = pc.LU + (size_t)blk * m * kPrecStride * P + (on ? p : 0);
   const size_t tsz = (size_t)P * W * W;
   const c2_t<TF>* TL = pc.TL + blk * tsz;
@@ -362,11 +364,11 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<TF>& pc, int
   // ---- lower solve, phase 1: local windows; tail t_p[c] = y[o + len - W + c] = win[W-1-c]
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_L1, MODE, W, D, TF>(LU, P, m, n, nk, io, nr, len, win, L);
+  substitute<T, SUB_L1, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
   __syncthreads();  // every lane is done with the staged steps
   if (on) {
 #pragma unroll
-    for (int c = 0; c < W; ++c) L.win[t][c] = win[W - 1 - c];
+    for (int c = 0; c < W; ++c) L.win[kk * P + p][c] = win[W - 1 - c];
   }
   __syncthreads();
   // ---- phase 2: group recurrences, group boundaries
@@ -383,16 +385,16 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<TF>& pc, int
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_L3, MODE, W, D, TF>(LU, P, m, n, nk, io, nr, len, win, L);
+  substitute<T, SUB_L3, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
 
   // ---- upper solve, phase 1: heads h_p[c] = x[o + c] = win[c] with zero incoming window
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_U1, MODE, W, D, TF>(LU, P, m, n, nk, io, nr, len, win, L);
+  substitute<T, SUB_U1, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
   __syncthreads();  // every thread has read its lower window
   if (on) {
 #pragma unroll
-    for (int c = 0; c < W; ++c) L.win[t][c] = win[c];
+    for (int c = 0; c < W; ++c) L.win[kk * P + p][c] = win[c];
   }
   __syncthreads();
   group_recurrence<T, false, W, TF>(TU, P, nc, nk, L);
@@ -408,7 +410,7 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<TF>& pc, int
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_U3, MODE, W, D, TF>(LU, P, m, n, nk, io, nr, len, win, L);
+  substitute<T, SUB_U3, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
 }
 
 }  // namespace tdde
