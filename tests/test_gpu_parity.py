@@ -385,15 +385,19 @@ def test_launch_shape_errors_and_autotune(gpu):
     s.close()
 
 
+@pytest.mark.parametrize("split", [False, True])
 @pytest.mark.parametrize("seg", [16, 48])
-def test_prec_segment_lengths_match_oracle(gpu, seg):
-    """Other least segment lengths of the preconditioner (refactored at set_dt) give the same steps."""
+def test_prec_segment_lengths_match_oracle(gpu, seg, split):
+    """Other least segment lengths of the preconditioner (refactored at set_dt) give the same steps, in
+    the persistent and the kernel-per-window solver. 600 rows: 16-row segments put 4 channels in a chain
+    work-group, 48-row segments 8, and the blocks with fewer channels leave channel slots empty."""
     P = _lib()
     w = dkb.config2(nr=300, r_max=60.0, lmax=3, driven=True)
     s = P.Solver(w.op, 1)
     try:
         with pytest.raises(P.TddeError):
             s.set_prec_segment(5)
+        s.set_split(split)
         s.set_prec_segment(seg)
         s.set_dt(w.dt)
         s.set_pulses(w.pulses)
