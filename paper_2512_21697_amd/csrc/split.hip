@@ -130,8 +130,7 @@ __device__ inline void sp_elems(const SplitArgs& a, const SpWg& w, F&& f) {
 
 // The same elements in batches of VB per thread: load(e) for the VB elements of a batch, then
 // compute(e, loaded) in element order (per-thread order as in sp_elems), so that a thread has the
-// loads of VB elements in flight at once (VB sized so that four waves per SIMD stay resident: the
-// grid holds four work-groups per CU).
+// loads of VB elements in flight at once.
 template <int kVB, typename LD, typename CP>
 __device__ inline void sp_elems_batched(const SplitArgs& a, const SpWg& w, LD&& load, CP&& compute) {
   const size_t base = (size_t)w.b * a.E;

@@ -624,12 +624,16 @@ tdde_status tdde_set_prec_segment(tdde_ctx* c, int32_t min_rows) {
   return TDDE_OK;
 }
 
-// Work-groups per instance of the kernel-per-window solver's apply and vector kernels: four per CU
-// over the batch (two rounds of the two-per-CU apply occupancy), a multiple of 8 so that work-group g
-// of every instance runs on XCD g % 8, and no more than the instance has tiles (rounded up to 8).
+// Work-groups per instance of the kernel-per-window solver's apply and vector kernels: two per CU
+// over the batch, the apply kernels' occupancy, so the whole grid is resident at once and every XCD
+// sweeps the channels of its radial tiles together (the neighbouring channels' tiles that the angular
+// gathers read are then still in its L2; a grid of two rounds measured 3 % slower per step, its second
+// half of work-groups starting only after the first had finished all of their tiles); a multiple of 8
+// so that work-group g of every instance runs on XCD g % 8, and no more than the instance has tiles
+// (rounded up to 8).
 static int split_wg(const tdde_ctx* c) {
   const long tiles = (long)c->op64.nang * c->op64.n_itiles;
-  long g = (4L * c->ncu / c->d.batch) / 8 * 8;
+  long g = (2L * c->ncu / c->d.batch) / 8 * 8;
   g = std::max(8L, std::min(g, (tiles + 7) / 8 * 8));
   return (int)g;
 }
