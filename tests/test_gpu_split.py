@@ -167,6 +167,41 @@ def test_split_batched_uneven_lengths(gpu):
         assert err < 1e-10 * n_steps[b], (b, err)
 
 
+def test_split_many_instances_smallest_grid(gpu):
+    """70 instances: the kernel-per-window grid takes its floor of 8 work-groups per instance (560 in
+    all, more than stay resident at once), every instance with its own length; each instance's state
+    against the oracle's steps."""
+    import paper_2512_21697_amd as P
+    B = 70
+    w = synthetic.config5(batch=B, nr=120, nang=4, seeds=list(range(20001, 20001 + B)))
+    rng = np.random.default_rng(7)
+    n_steps = rng.integers(1, 4, size=B).astype(np.int32)
+    s = P.Solver(w.op, B)
+    try:
+        s.set_dt(w.dt)
+        s.set_pulses(w.pulses)
+        s.set_split(True)
+        n_wg, per_inst = s.launch_info()
+        assert per_inst == 8 and n_wg == 8 * B, (n_wg, per_inst)
+        psi = torch.from_numpy(np.ascontiguousarray(w.psi0.reshape(-1))).to(DEV)
+        stats = torch.zeros(3 * B * 40, dtype=torch.uint8, device=DEV)
+        print("split 70 instances", flush=True)
+        s.run_batched(psi, w.t0, 0, 3, n_steps, P.solve_opts(tol=1e-12, guess=P.GUESS_PREV), stats)
+        torch.cuda.synchronize()
+        got = psi.cpu().numpy().reshape(B, w.op.nang, 2, w.op.nr)
+        st = np.frombuffer(stats.cpu().numpy().tobytes(), dtype=P.STATS_DTYPE).reshape(3, B)
+    finally:
+        s.close()
+    asm = Assembled(w.op)
+    for b in range(B):
+        ref = w.psi0[b]
+        for k in range(int(n_steps[b])):
+            ref, _ = cn_step(asm, w.pulses[b], w.t0 + k * w.dt, w.dt, ref, solver="splu")
+            assert st[k, b]["status"] == 0 and st[k, b]["iters"] >= 1, (b, k, st[k, b])
+        err = np.linalg.norm(got[b] - ref) / np.linalg.norm(ref)
+        assert err < 1e-10 * n_steps[b], (b, err)
+
+
 def test_split_single_step(gpu):
     import paper_2512_21697_amd as P
     w = dkb.config2(nr=300, r_max=60.0, lmax=3, driven=True, E0=0.5)
