@@ -50,14 +50,16 @@ template <typename T> struct DevPrec {
   const c2_t<T>* CU;       // [nblk][w][w][P] upper group products
 };
 
-// Steps of every segment staged through LDS at a time in the substitutions, and the row pitch of the
-// staging array (kMaxSeg + 2: the cooperative writes of 2 segments x 8 steps per 16 lanes hit 16
+// Steps of every segment staged through LDS at a time in the substitutions, at most (one staging
+// round trip per chunk: 16 is the most that keeps two chain work-groups per CU; segments whose length
+// is not a multiple of 16 take chunks of 8, see substitute_chunked), and the row pitch of the staging
+// array (kMaxSeg + 2: the cooperative writes of one segment's consecutive steps by 16 lanes hit 16
 // different 16-byte bank groups).
-constexpr int kStageRows = 8;
+constexpr int kStageRows = 16;
 constexpr int kStagePitch = kMaxSeg + 2;
 
 // LDS of one chain solve: the boundary window of every segment and the true boundary of every
-// segment group (phase 2); during the substitutions the windows' space holds the staged steps.
+// segment group (phase 2); the staged steps of the substitutions share the windows' space.
 constexpr int kMaxChainNc = 8;  // channels of one work-group
 
 template <typename T> struct ChainLds {
@@ -68,7 +70,7 @@ template <typename T> struct ChainLds {
   c2_t<T> u[kMaxSegGroups][kPrecW];
   long coff[kMaxChainNc];  // element offset of every channel of the work item within the instance
 };
-static_assert(kStageRows * kStagePitch <= kMaxSeg * kPrecW, "staged steps must fit the windows' space");
+static_assert(sizeof(ChainLds<double>) <= 80 * 1024, "two chain work-groups per CU");
 
 // Channels of chain work item w (pc.chain_order row): count of valid entries (0 for a padding item).
 template <typename T> __device__ inline int chain_item(const DevPrec<T>& pc, int w, const int*& js) {
@@ -170,13 +172,13 @@ __device__ inline c2_t<T> stage_input(const ChainIO<T>& io, long e) {
 // wave's loads are runs of whole pieces instead of one element per segment m / 2 elements apart),
 // every lane substitutes its rows from LDS, and phase-3 kinds write their results back through LDS
 // the same way. Phase-1 kinds keep only the window. All threads call (barriers inside).
-template <typename T, int KIND, int MODE, int W, int D = kChainAhead, typename TF = T>
+template <typename T, int KIND, int MODE, int W, int D, typename TF, int C>
 __device__ inline void substitute(const c2_t<TF>* LU, int P, int m, int n, int nc, int nk, const ChainIO<T>& io, int nr,
                                   int len, c2_t<T> (&win)[W], ChainLds<T>& L) {
   constexpr bool lower = KIND <= SUB_L3;
   constexpr bool writes = KIND == SUB_L3 || KIND == SUB_U3;
   constexpr int NC = lower ? W : W + 1;
-  constexpr int C = kStageRows;
+  static_assert(C <= kStageRows, "chunk larger than the staging array");
   static_assert(C % D == 0, "the steps of a chunk must be whole rounds of the lookahead");
   const int lane = threadIdx.x;
   const int nl = nc * P;  // lanes that may hold a segment (those of channel slots kk >= nk hold none)
@@ -226,6 +228,16 @@ __device__ inline void substitute(const c2_t<TF>* LU, int P, int m, int n, int n
       }
     }
   }
+}
+
+// The substitution in chunks of 16 steps when the segment length is a multiple of 16, else of 8 (a
+// 16-step chunk over 24-row segments leaves half of every second chunk empty: the hydrogen step
+// measured 2-7 % slower with it, the 64-row beyond-dipole step 1.4 % faster).
+template <typename T, int KIND, int MODE, int W, int D = kChainAhead, typename TF = T>
+__device__ inline void substitute_chunked(const c2_t<TF>* LU, int P, int m, int n, int nc, int nk,
+                                          const ChainIO<T>& io, int nr, int len, c2_t<T> (&win)[W], ChainLds<T>& L) {
+  if (m % 16 == 0) substitute<T, KIND, MODE, W, D, TF, 16>(LU, P, m, n, nc, nk, io, nr, len, win, L);
+  else substitute<T, KIND, MODE, W, D, TF, 8>(LU, P, m, n, nc, nk, io, nr, len, win, L);
 }
 
 // Ordering of LDS accesses between lanes of one wave: a wave executes its LDS operations in issue
@@ -364,7 +376,7 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<TF>& pc, int
   // ---- lower solve, phase 1: local windows; tail t_p[c] = y[o + len - W + c] = win[W-1-c]
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_L1, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
+  substitute_chunked<T, SUB_L1, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
   __syncthreads();  // every lane is done with the staged steps
   if (on) {
 #pragma unroll
@@ -385,12 +397,12 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<TF>& pc, int
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_L3, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
+  substitute_chunked<T, SUB_L3, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
 
   // ---- upper solve, phase 1: heads h_p[c] = x[o + c] = win[c] with zero incoming window
 #pragma unroll
   for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
-  substitute<T, SUB_U1, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
+  substitute_chunked<T, SUB_U1, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
   __syncthreads();  // every thread has read its lower window
   if (on) {
 #pragma unroll
@@ -410,7 +422,7 @@ __device__ __attribute__((noinline)) void chain_solve(const DevPrec<TF>& pc, int
 #pragma unroll
     for (int k = 0; k < W; ++k) win[k] = cmk<T>(0, 0);
   }
-  substitute<T, SUB_U3, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
+  substitute_chunked<T, SUB_U3, MODE, W, D, TF>(LU, P, m, n, nc, nk, io, nr, len, win, L);
 }
 
 }  // namespace tdde
